@@ -1,0 +1,93 @@
+"""Projected L-BFGS (test infrastructure only).
+
+Paper section 2.3.1: L-BFGS (limited-memory quasi-Newton, Nocedal & Wright
+two-loop recursion) whose line search moves along s' = P(s + eps p) instead of
+s + eps p, P being the projection of ``oracle.projection``.  Appendix B sets
+the maximum step eps_max = 1 for the method.
+
+Readings where the paper is silent: backtracking from eps_max, halving, up to
+30 trials, Armijo test L(s') <= L(s) + c1 eps (g . p) with c1 = 1e-4 against
+the unprojected directional derivative; initial inverse Hessian gamma I with
+gamma = S.Y / Y.Y of the newest pair (1 with an empty history, natural since
+the prior's Hessian is the identity); a pair is stored only when
+S.Y > 1e-10 |S| |Y|; the history holds m = 10 pairs; a non-descent direction
+resets the history and falls back to -g.  All dot products are FP64.
+"""
+import numpy as np
+
+from .projection import project
+
+__all__ = ["ProjectedLBFGS", "LineSearchError"]
+
+
+class LineSearchError(RuntimeError):
+    pass
+
+
+class ProjectedLBFGS:
+    def __init__(self, m=10, eps_max=1.0, c1=1e-4, max_trials=30, s_th=10.0,
+                 seed=0, curvature_eps=1e-10):
+        self.m, self.eps_max, self.c1 = m, eps_max, c1
+        self.max_trials, self.s_th, self.seed = max_trials, s_th, seed
+        self.curvature_eps = curvature_eps
+        self.S, self.Y = [], []
+
+    def reset(self):
+        self.S, self.Y = [], []
+
+    def direction(self, g):
+        """p = -H g by the two-loop recursion."""
+        q = np.array(g, dtype=np.float64)
+        alpha = []
+        for S, Y in zip(reversed(self.S), reversed(self.Y)):
+            rho = 1.0 / np.dot(S, Y)
+            a = rho * np.dot(S, q)
+            q = q - a * Y
+            alpha.append(a)
+        gamma = 1.0
+        if self.S:
+            gamma = np.dot(self.S[-1], self.Y[-1]) / np.dot(self.Y[-1], self.Y[-1])
+        r = gamma * q
+        for (S, Y), a in zip(zip(self.S, self.Y), reversed(alpha)):
+            rho = 1.0 / np.dot(S, Y)
+            b = rho * np.dot(Y, r)
+            r = r + (a - b) * S
+        return -r
+
+    def step(self, s, g, L, fun, iteration):
+        """One projected L-BFGS iteration.
+
+        fun(s) -> (L, g).  Returns (s', g', L', info)."""
+        s = np.asarray(s, dtype=np.float64).reshape(-1)
+        g = np.asarray(g, dtype=np.float64).reshape(-1)
+        p = self.direction(g)
+        gp = float(np.dot(g, p))
+        restarted = False
+        if not gp < 0:
+            self.reset()
+            p = -g
+            gp = float(np.dot(g, p))
+            restarted = True
+        eps = self.eps_max
+        for trial in range(self.max_trials):
+            s_t, resets = project(s + eps * p, self.s_th, self.seed, iteration, trial)
+            L_t, g_t = fun(s_t)
+            g_t = np.asarray(g_t, dtype=np.float64).reshape(-1)
+            if L_t <= L + self.c1 * eps * gp:
+                break
+            eps *= 0.5
+        else:
+            raise LineSearchError("no acceptable step in %d trials" % self.max_trials)
+        S = s_t - s
+        Y = g_t - g
+        sy = float(np.dot(S, Y))
+        stored = sy > self.curvature_eps * np.sqrt(np.dot(S, S) * np.dot(Y, Y))
+        if stored:
+            self.S.append(S)
+            self.Y.append(Y)
+            if len(self.S) > self.m:
+                self.S.pop(0)
+                self.Y.pop(0)
+        info = dict(eps=eps, trials=trial + 1, resets=resets, stored=bool(stored),
+                    restarted=restarted, history=len(self.S), gp=gp)
+        return s_t, g_t, L_t, info

@@ -1,0 +1,222 @@
+"""Pins of the oracle's counter generator, projection, rank-order matching and
+projected L-BFGS (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import fourier, lbfgs, philox, projection, rom
+
+
+# ----------------------------------------------------------------- Philox
+@pytest.mark.parametrize("ctr", [0, 7, 2 ** 40 + 3])
+def test_philox_matches_numpy_bit_generator(ctr):
+    """numpy's Philox4x64-10 advances its counter before the first block."""
+    key = 0x1234ABCD
+    bg = np.random.Philox(key=np.array([key, 0], dtype=np.uint64),
+                          counter=np.array([ctr, 0, 0, 0], dtype=np.uint64))
+    raw = bg.random_raw(8)
+    ours = [philox.philox4x64(ctr + 1 + b, 0, 0, 0, key) for b in range(2)]
+    ours = np.array([int(w) for blk in ours for w in blk], dtype=np.uint64)
+    assert np.array_equal(raw, ours)
+
+
+def test_philox_high_counter_words():
+    """Counter words 1..3 as numpy sees them after a carry."""
+    key = 99
+    c = np.array([2 ** 64 - 1, 5, 6, 7], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([key, 0], dtype=np.uint64), counter=c)
+    raw = bg.random_raw(4)
+    ours = philox.philox4x64(0, 6, 6, 7, key)
+    assert np.array_equal(raw, np.array([int(w) for w in ours], dtype=np.uint64))
+
+
+def test_draw_distributions():
+    j = np.arange(200000, dtype=np.uint64)
+    z = philox.normal(j, 0, 2, 5, 77)
+    a = philox.rayleigh(j, 3, 3, 5, 77)
+    assert abs(z.mean()) < 0.01 and abs(z.var() - 1) < 0.01
+    assert abs(np.mean(a * a) - 1) < 0.01
+    u0, u1 = philox.uniform_pair(j, 0, 1, 0, 77)
+    assert u0.min() > 0 and u0.max() < 1 and u1.min() > 0 and u1.max() < 1
+
+
+# ------------------------------------------------------------- projection
+def test_projection_zscore_without_resets():
+    s = np.random.default_rng(20).normal(0.3, 2.0, size=(16, 16, 16))
+    out, nres = projection.project(s, 10.0, 1, 0, 0)
+    assert nres == 0
+    assert abs(out.mean()) <= 1e-15
+    assert abs(out.std() - 1.0) <= 1e-15
+
+
+def test_projection_resets_planted_values():
+    rng = np.random.default_rng(21)
+    s = rng.standard_normal(4096)
+    planted = [5, 77, 1000]
+    s[planted] = [400.0, -350.0, 500.0]
+    out, nres = projection.project(s, 10.0, 9, 3, 2)
+    assert nres == 3
+    ref = philox.normal(np.array(planted, dtype=np.uint64), 2, philox.STREAM_RESET, 3, 9)
+    assert np.array_equal(out[planted], ref)
+    keep = np.setdiff1d(np.arange(4096), planted)
+    mu = s.mean()
+    sd = np.sqrt(np.mean((s - mu) ** 2))
+    assert np.allclose(out[keep], (s[keep] - mu) / sd, rtol=0, atol=1e-15)
+
+
+def test_projection_is_almost_identity_on_gaussian_samples():
+    """Section 2.3.1: P(s) = s + O(1/d) for Gaussian s; the mean-square shift
+    per element falls as 1/d."""
+    ds, ms = [], []
+    for d in [1000, 4000, 16000, 64000]:
+        acc = []
+        for t in range(40):
+            s = np.random.default_rng(1000 * d + t).standard_normal(d)
+            out, _ = projection.project(s, 10.0, 0, 0, 0)
+            acc.append(np.mean((out - s) ** 2))
+        ds.append(d)
+        ms.append(np.mean(acc))
+    slope = np.polyfit(np.log(ds), np.log(ms), 1)[0]
+    assert abs(slope + 1.0) <= 0.1
+
+
+# -------------------------------------------------------------------- ROM
+def brute_ranks(x):
+    """rank_i = number of elements strictly greater, plus equal ones before."""
+    n = len(x)
+    r = [0] * n
+    for i in range(n):
+        for j in range(n):
+            if x[j] > x[i] or (x[j] == x[i] and j < i):
+                r[i] += 1
+    return r
+
+
+def test_descending_order_matches_brute_force_with_ties_and_signed_zero():
+    x = np.array([0.5, -0.0, 2.0, 0.0, 0.5, -1.0, 2.0, 0.0, -0.0, 3.0])
+    o = rom.descending_order(x)
+    ranks = np.empty(len(x), dtype=int)
+    ranks[o] = np.arange(len(x))
+    assert list(ranks) == brute_ranks(list(x))
+    with pytest.raises(ValueError):
+        rom.descending_order(np.array([1.0, np.nan]))
+
+
+def test_match_properties():
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal(500)
+    t = rng.standard_normal(500)
+    out, o = rom.match(x, t)
+    assert np.array_equal(np.sort(out), np.sort(t))           # multiset, bitwise
+    assert np.array_equal(np.argsort(-out, kind="stable"), o)  # ranks preserved
+    same, _ = rom.match(x, x)
+    assert np.array_equal(same, x)                             # identity
+
+
+def test_match_error_scales_as_inverse_sqrt_n():
+    """Section 2.3.2: on an input that already follows p(x) the matching
+    moves each value by O(1/sqrt(N))."""
+    ns, errs = [], []
+    for n in [1000, 4000, 16000, 64000]:
+        acc = []
+        for t in range(20):
+            rng = np.random.default_rng(n + t)
+            x = rng.standard_normal(n)
+            out, _ = rom.match(x, rng.standard_normal(n))
+            acc.append(np.sqrt(np.mean((out - x) ** 2)))
+        ns.append(n)
+        errs.append(np.mean(acc))
+    slope = np.polyfit(np.log(ns), np.log(errs), 1)[0]
+    assert abs(slope + 0.5) <= 0.1
+
+
+def test_rom_real_only_touches_masked_cells():
+    rng = np.random.default_rng(23)
+    s = rng.standard_normal((8, 8, 8))
+    R = (rng.uniform(size=(8, 8, 8)) > 0.5).astype(float)
+    out, info = rom.rom_real(s, R, 1e-3, 5, 1)
+    m = R >= 1e-3
+    assert np.array_equal(out[~m], s[~m])
+    t = philox.normal(np.arange(m.sum(), dtype=np.uint64), 0, philox.STREAM_ROM_REAL, 1, 5)
+    assert np.array_equal(np.sort(out[m]), np.sort(t))
+
+
+def test_rom_fourier_properties():
+    n, L = 16, 128.0
+    s = np.random.default_rng(24).standard_normal((n, n, n))
+    out, info = rom.rom_fourier(s, L, 7, 2)
+    z0 = fourier.rfft3(s) / n ** 1.5
+    z1 = fourier.rfft3(out) / n ** 1.5
+    idx, bins, partner = rom.fourier_mode_sets(n, L)
+    touched = np.zeros(z0.size, bool)
+    touched[idx] = True
+    touched[partner[partner >= 0]] = True
+    assert np.max(np.abs(z1.reshape(-1)[~touched] - z0.reshape(-1)[~touched])) <= 1e-12
+    for b in range(100):
+        sel = np.nonzero(bins == b)[0]
+        if sel.size == 0:
+            continue
+        amp = np.abs(z1.reshape(-1)[idx[sel]])
+        t = philox.rayleigh(np.arange(sel.size, dtype=np.uint64), b,
+                            philox.STREAM_ROM_FOURIER, 2, 7)
+        assert np.allclose(np.sort(amp), np.sort(t), rtol=1e-12, atol=1e-12)
+        ph0 = np.angle(z0.reshape(-1)[idx[sel]])
+        ph1 = np.angle(z1.reshape(-1)[idx[sel]])
+        assert np.max(np.abs(np.angle(np.exp(1j * (ph1 - ph0))))) <= 1e-10
+    # the modes below k_min and the self-conjugate modes are untouched
+    k = fourier.kgrid(n, L).reshape(-1)
+    assert not touched[k < 0.1].any()
+
+
+def test_fourier_mode_sets_cover_each_conjugate_pair_once():
+    n, L = 8, 8.0  # k_min below the fundamental: every non-DC mode qualifies
+    idx, bins, partner = rom.fourier_mode_sets(n, L)
+    nh = n // 2 + 1
+    # count real degrees of freedom: 2 per independent complex mode
+    selfconj = 8  # kx, ky, kz each in {0, N/2}
+    dof = 2 * len(idx) + selfconj
+    assert dof == n ** 3
+    assert len(set(idx.tolist()) & set(partner[partner >= 0].tolist())) == 0
+
+
+# ----------------------------------------------------------------- L-BFGS
+def test_two_loop_equals_explicit_bfgs_matrix():
+    rng = np.random.default_rng(25)
+    d = 30
+    opt = lbfgs.ProjectedLBFGS(m=50)
+    A = rng.standard_normal((d, d))
+    A = A @ A.T + d * np.eye(d)
+    for _ in range(12):
+        S = rng.standard_normal(d)
+        opt.S.append(S)
+        opt.Y.append(A @ S)
+    Sl, Yl = opt.S, opt.Y
+    gamma = Sl[-1] @ Yl[-1] / (Yl[-1] @ Yl[-1])
+    H = gamma * np.eye(d)
+    for S, Y in zip(Sl, Yl):
+        rho = 1.0 / (S @ Y)
+        V = np.eye(d) - rho * np.outer(Y, S)
+        H = V.T @ H @ V + rho * np.outer(S, S)
+    g = rng.standard_normal(d)
+    p = opt.direction(g)
+    assert np.allclose(p, -H @ g, rtol=1e-12, atol=1e-12)
+    assert np.allclose(H @ Yl[-1], Sl[-1], rtol=1e-12, atol=1e-12)   # secant
+
+
+def test_projected_lbfgs_monotone_on_quadratic():
+    """On a convex quadratic whose minimiser is unaffected by the projection
+    scale, every accepted step satisfies Armijo and lowers the loss."""
+    rng = np.random.default_rng(26)
+    d = 4096
+    target = rng.standard_normal(d)
+    target = (target - target.mean()) / target.std()
+    diag = rng.uniform(1.0, 5.0, d)
+    fun = lambda s: (0.5 * np.sum(diag * (s - target) ** 2), diag * (s - target))
+    opt = lbfgs.ProjectedLBFGS(seed=3)
+    s, _ = projection.project(rng.standard_normal(d), 10.0, 3, 0, 0)
+    L, g = fun(s)
+    for k in range(15):
+        s2, g2, L2, info = opt.step(s, g, L, fun, k)
+        assert L2 <= L + 1e-4 * info["eps"] * info["gp"]
+        assert L2 < L
+        s, g, L = s2, g2, L2
+    assert L < 1e-2 * fun(projection.project(rng.standard_normal(d), 10, 3, 0, 0)[0])[0]
