@@ -1,0 +1,203 @@
+/*
+ * ic_api.h - C ABI of the MI355X (gfx950) implementation of the MUJICA
+ * initial-condition reconstruction hot path (arXiv 2604.26823).
+ *
+ * The library evaluates the differentiable forward model of paper section
+ * 2.2.1 (white noise -> BBKS-shaped linear field -> 2LPT -> FastPM kick-drift-
+ * kick particle mesh -> redshift-space distortion -> linear bias and survey
+ * response), the masked Gaussian chi^2 plus white-noise prior built on it,
+ * the gradient of that loss by a hand-written adjoint, the projection and
+ * rank-order matching of section 2.3, and the projected L-BFGS step of
+ * section 2.3.1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every int-returning call returns IC_OK (0) or a negative IC_ERR_*
+ *   code; ic_last_error() then describes the failure.  Nothing aborts or
+ *   throws across the ABI.
+ * Ownership: the caller allocates every device buffer: fields passed to the
+ *   calls and one workspace block of ic_workspace_size() bytes handed to
+ *   ic_create().  The library never allocates or frees device memory and
+ *   keeps the workspace, observation and stream pointers until ic_destroy(),
+ *   so the caller keeps them alive.  Host pointers (loss, info structs,
+ *   debug dumps) are written before the call returns.
+ * Streams: all device work is enqueued on the hipStream_t given to
+ *   ic_create() / ic_set_stream().  Calls that return host values (losses,
+ *   info structs, debug dumps) synchronise that stream; the rest are
+ *   asynchronous.  A context is not thread-safe.
+ * Precision: fixed per context, IC_F32 or IC_F64.  All field buffers have
+ *   that element type; losses and optimiser scalars are always double.
+ * Layouts: real fields are C-ordered [x][y][z] cubes of side n_part (the
+ *   white-noise, particle and data grid) with z fastest.  Particle arrays are
+ *   structure-of-arrays [3][n_part^3] in the same lattice order.
+ * Shapes: n_part a power of two in [8, 512]; n_mesh = n_part or 2 n_part and
+ *   at most 1024; otherwise IC_ERR_UNSUPPORTED.
+ */
+#ifndef IC_API_H
+#define IC_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IC_ABI_VERSION 1
+
+#define IC_OK 0
+#define IC_ERR_INVALID_ARG (-1)
+#define IC_ERR_UNSUPPORTED (-2)
+#define IC_ERR_WORKSPACE (-3)
+#define IC_ERR_HIP (-4)
+#define IC_ERR_NONFINITE (-5)
+#define IC_ERR_LINESEARCH (-6)
+#define IC_ERR_STATE (-7)
+
+#define IC_F32 0
+#define IC_F64 1
+
+#define IC_RSD_NONE 0
+#define IC_RSD_AXIS_Z 1
+#define IC_RSD_RADIAL 2
+
+/* flags of ic_project_rankmatch */
+#define IC_PROJECT 1u
+#define IC_ROM_REAL 2u
+#define IC_ROM_FOURIER 4u
+
+/* Method parameters the paper fixes (section 2.3.1: reset threshold;
+ * section 2.3.2: 100 equal-width k bins, modes below k = 0.1 h/Mpc left
+ * alone; section 2.2.1 item 2: 2LPT to a = 0.1; appendix B, table 1: the
+ * method's maximum line-search step). */
+#define IC_DEFAULT_S_TH 10.0
+#define IC_DEFAULT_ROM_NBINS 100
+#define IC_DEFAULT_ROM_KMIN 0.1
+#define IC_DEFAULT_A_INIT 0.1
+#define IC_DEFAULT_EPS_MAX 1.0
+
+/* The reconstruction problem (sections 2.2-2.3).  Lengths in Mpc/h. */
+typedef struct ic_problem {
+  int32_t n_part;        /* particles per side = white-noise and data grid side */
+  int32_t n_mesh;        /* particle-mesh force grid side (n_part or 2 n_part) */
+  int32_t n_steps;       /* kick-drift-kick steps, linear in a, >= 1 */
+  int32_t rsd_mode;      /* IC_RSD_NONE, IC_RSD_AXIS_Z or IC_RSD_RADIAL */
+  double box;            /* periodic box side */
+  double a_init;         /* 2LPT start (0.1) */
+  double a_final;        /* output epoch (1.0) */
+  double omega_m, h, n_s, sigma8;   /* flat LCDM, BBKS transfer function */
+  double observer[3];    /* observer position for radial RSD */
+  double bias;           /* linear bias b: lambda = nbar R (1 + b delta_s) */
+  double nbar;           /* mean galaxies per data cell */
+  double r_min;          /* mask M = [R >= r_min] */
+  double prior_weight;   /* weight of 1/2 |s|^2 in the loss */
+  int32_t lbfgs_m;       /* history pairs (10) */
+  int32_t max_trials;    /* line-search trials (30) */
+  double eps_max;        /* first trial step (1.0) */
+  double armijo_c1;      /* sufficient-decrease constant (1e-4) */
+  double s_th;           /* projection reset threshold (10) */
+  int32_t rom_nbins;     /* Fourier-space matching bins (100) */
+  int32_t tape_forces;   /* 1: keep force meshes for the adjoint; 0: recompute */
+  double rom_kmin;       /* smallest matched |k| (0.1 h/Mpc) */
+  uint64_t seed;         /* key of the counter-based generator */
+} ic_problem;
+
+typedef struct ic_loss_terms {
+  double loss;           /* 1/2 chi2 + 1/2 prior_weight |s|^2 */
+  double chi2;           /* sum over masked cells of (N - lambda)^2 / (nbar R) */
+  double prior;          /* |s|^2 */
+  int64_t n_masked;      /* cells with R >= r_min */
+} ic_loss_terms;
+
+typedef struct ic_lbfgs_info {
+  double eps;            /* accepted step */
+  double gp;             /* g . p of the search direction */
+  int32_t trials;        /* line-search trials used */
+  int32_t evaluations;   /* loss+gradient evaluations made */
+  int32_t stored;        /* 1 if the (S, Y) pair entered the history */
+  int32_t history;       /* pairs held after the step */
+  int32_t restarted;     /* 1 if the direction was reset to -g */
+  int32_t resets;        /* projection resets in the accepted trial */
+} ic_lbfgs_info;
+
+typedef struct ic_rom_info {
+  int64_t n_real;        /* elements matched in real space */
+  int64_t n_fourier;     /* modes matched in Fourier space */
+  int32_t resets;        /* projection resets */
+  int32_t bins_used;     /* non-empty k bins */
+} ic_rom_info;
+
+typedef struct ic_ctx ic_ctx;
+
+/* ABI version (IC_ABI_VERSION). */
+int32_t ic_abi_version(void);
+
+/* Fills *p with the defaults above (n_part, n_mesh, box, rsd_mode left 0). */
+void ic_problem_defaults(ic_problem* p);
+
+/* Device bytes the workspace of a context for (*p, precision) needs. */
+int ic_workspace_size(const ic_problem* p, int precision, size_t* bytes);
+
+/* Validates *p, lays out the caller's workspace (device pointer ws of
+ * ws_bytes bytes, 256-byte aligned) and computes the FP64 cosmology
+ * coefficients (growth factors, FastPM kick/drift factors of section 2.2.1
+ * item 2, whitening multiplier of item 1).  stream: a hipStream_t (NULL =
+ * default stream).  *out receives the context. */
+int ic_create(const ic_problem* p, int precision, void* ws, size_t ws_bytes,
+              void* stream, ic_ctx** out);
+
+/* Releases the context (host memory only; device buffers stay the caller's). */
+void ic_destroy(ic_ctx* ctx);
+
+/* Description of the last failure on ctx (or of the last failed ic_create
+ * when ctx is NULL). */
+const char* ic_last_error(const ic_ctx* ctx);
+
+/* Changes the stream later calls enqueue on. */
+int ic_set_stream(ic_ctx* ctx, void* stream);
+
+/* Observation of section 2.2.1 items 4-5 and 2.2.2: galaxy counts N
+ * (int32, device, n_part^3) and survey response R (device, context
+ * precision, n_part^3).  Mask M = [R >= r_min]; variance nbar R.  The
+ * pointers are kept; the caller keeps the buffers alive and unchanged. */
+int ic_set_observation(ic_ctx* ctx, const int32_t* counts, const void* response);
+
+/* Forward model s -> delta_s (section 2.2.1).  s: device, n_part^3.
+ * delta_s, lambda: optional device outputs (n_part^3, NULL to skip).
+ * loss: optional host output (needs an observation). */
+int ic_forward(ic_ctx* ctx, const void* s, void* delta_s, void* lambda, double* loss);
+
+/* L(s) = 1/2 chi^2 + 1/2 prior_weight |s|^2 and its gradient (device,
+ * n_part^3) by the hand-written adjoint of the forward model.  terms is
+ * optional.  Returns IC_ERR_NONFINITE when L or the gradient is not finite. */
+int ic_loss_and_grad(ic_ctx* ctx, const void* s, void* grad, double* loss,
+                     ic_loss_terms* terms);
+
+/* Vector-Jacobian product s_bar = J^T delta_bar of s -> delta_s (no prior);
+ * all device buffers of n_part^3. */
+int ic_vjp(ic_ctx* ctx, const void* s, const void* delta_bar, void* s_bar);
+
+/* In-place projection and rank-order matching of the white noise s
+ * (sections 2.3.1-2.3.2), in the order projection, real-space matching on
+ * M = 1 cells, Fourier-space matching of |z| per k bin; flags selects the
+ * parts.  event keys the random draws (reset draws also use trial).
+ * info is optional.  A rank-order pass fails with IC_ERR_NONFINITE on NaN. */
+int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
+                         int32_t trial, ic_rom_info* info);
+
+/* One projected L-BFGS iteration (section 2.3.1): direction from the
+ * two-loop recursion over the stored pairs (FP64 dot products), backtracking
+ * line search along P(s + eps p) from eps_max with the Armijo test, history
+ * update.  s, grad: device in/out (n_part^3); loss: host in/out; iteration
+ * keys the reset draws.  Returns IC_ERR_LINESEARCH when no trial passes. */
+int ic_lbfgs_step(ic_ctx* ctx, void* s, void* grad, double* loss, int64_t iteration,
+                  ic_lbfgs_info* info);
+
+/* Clears the L-BFGS history (after a rank-order matching event). */
+int ic_lbfgs_reset(ic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IC_API_H */

@@ -1,0 +1,225 @@
+// Engine members for rank-order matching (paper section 2.3.2) and the
+// projected L-BFGS iteration (section 2.3.1).  Included by engine_impl.h.
+#pragma once
+
+#include "rom.h"
+
+namespace ic {
+
+namespace ek {
+// Count of entries of v below thr -> part[block] (FP64 counts).
+static __global__ __launch_bounds__(fk::kRedThreads) void k_count_below(const uint32_t* __restrict__ v,
+                                                                 uint32_t thr,
+                                                                 double* __restrict__ part,
+                                                                 long long n) {
+  __shared__ double sh[fk::kRedThreads / 64];
+  double c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if (v[i] < thr) c += 1.0;
+  c = fk::block_sum(c, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = c;
+}
+
+static __global__ void k_u64_to_u32(const uint64_t* __restrict__ a, uint32_t* __restrict__ b,
+                             long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = static_cast<uint32_t>(a[i]);
+}
+
+static __global__ void k_fill_u32(uint32_t* __restrict__ a, uint32_t v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+}  // namespace ek
+
+// Real space: the cells with R >= r_min, ranked by the white noise in
+// descending order (ties by cell index), receive the sorted N(0,1) targets.
+template <typename T>
+long long Engine<T>::rom_real(T* s, uint64_t event) {
+  const unsigned G = grid_for(P_, kThreads);
+  const int vbits = 8 * sizeof(T);
+  rk::k_real_keys<T><<<G, kThreads, 0, st_>>>(s, resp_, static_cast<T>(prob_.r_min), keys_,
+                                              vals_, small_, P_);
+  IC_LAUNCHED();
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, P_, vbits, st_);
+  sk::k_gather_u32_key<<<G, kThreads, 0, st_>>>(small_, vals_, keys_, P_);
+  IC_LAUNCHED();
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, P_, 4, st_);
+  const unsigned g = grid_for(P_, fk::kRedThreads, kRedBlocks);
+  ek::k_count_below<<<g, fk::kRedThreads, 0, st_>>>(small_, 1u, part_, P_);
+  IC_LAUNCHED();
+  double cnt = 0;
+  reduce_parts(g, 1, &cnt);
+  const long long n = (long long)cnt;
+  dbg_n_[0] = n;
+  if (n == 0) return 0;
+  IC_HIP(hipMemcpyAsync(dbg_idx_[0], vals_, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st_));
+  rk::k_gather<T><<<grid_for(n, kThreads), kThreads, 0, st_>>>(s, dbg_idx_[0], dbg_key_[0], n);
+  IC_LAUNCHED();
+  rk::k_real_targets<T><<<grid_for(n, kThreads), kThreads, 0, st_>>>(event, prob_.seed, tbuf_,
+                                                                      keys_, vals_, n);
+  IC_LAUNCHED();
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, vbits, st_);
+  rk::k_scatter_sorted<T><<<grid_for(n, kThreads), kThreads, 0, st_>>>(s, dbg_idx_[0], tbuf_,
+                                                                        vals_, n);
+  IC_LAUNCHED();
+  return n;
+}
+
+// Fourier space: z = rfft(s) / N^(3/2); independent modes with |k| >= k_min,
+// per equal-width k bin, ranked by |z| (ties by half-spectrum index), get the
+// sorted Rayleigh targets of their bin; phases are kept and conjugate
+// partners mirrored before the inverse transform.
+template <typename T>
+long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
+  auto f = fa(0);
+  cx<T>* Z = pool_;
+  fft_r2c_z<T>(f, s, T(1), nullptr, T(0), Z);
+  fft_y<T>(f, Z, true);
+  fft_x<T>(f, Z, Z, true, T(1));
+  const double n3h = std::pow((double)np_, 1.5);
+  const int nbins = prob_.rom_nbins;
+  if (nbins < 1 || nbins > 254) throw ApiError(IC_ERR_INVALID_ARG, "rom_nbins must be in [1, 254]");
+  const double kf = 2.0 * 3.14159265358979323846 / prob_.box;
+  const double kmax = std::sqrt(3.0) * 3.14159265358979323846 * np_ / prob_.box;
+  const double dk = (kmax - prob_.rom_kmin) / nbins;
+  const unsigned G = grid_for(Hp_, kThreads);
+  const int vbits = 8 * sizeof(T);
+  rk::k_mode_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, static_cast<T>(1.0 / n3h), kf,
+                                              prob_.rom_kmin, dk, nbins, vbuf_, keys_, vals_,
+                                              small_, Hp_);
+  IC_LAUNCHED();
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hp_, vbits, st_);
+  sk::k_gather_u32_key<<<G, kThreads, 0, st_>>>(small_, vals_, keys_, Hp_);
+  IC_LAUNCHED();
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hp_, 8, st_);
+  ek::k_fill_u32<<<1, 256, 0, st_>>>(binc_, 0u, 256);
+  IC_LAUNCHED();
+  rk::k_bin_count<<<G, kThreads, 0, st_>>>(keys_, binc_, Hp_);
+  IC_LAUNCHED();
+  std::vector<uint32_t> counts(256);
+  IC_HIP(hipMemcpyAsync(counts.data(), binc_, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
+  IC_HIP(hipStreamSynchronize(st_));
+  std::vector<uint32_t> start(128, 0);
+  long long n = 0;
+  int used = 0;
+  for (int b = 0; b < nbins; ++b) {
+    start[b] = static_cast<uint32_t>(n);
+    n += counts[b];
+    used += counts[b] > 0;
+  }
+  if (bins_used) *bins_used = used;
+  dbg_n_[1] = n;
+  if (n > 0) {
+    IC_HIP(hipMemcpyAsync(binc_ + 128, start.data(), 128 * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, st_));
+    IC_HIP(hipMemcpyAsync(dbg_idx_[1], vals_, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st_));
+    const unsigned Gn = grid_for(n, kThreads);
+    ek::k_u64_to_u32<<<Gn, kThreads, 0, st_>>>(keys_, dbg_bin_, n);
+    IC_LAUNCHED();
+    rk::k_gather<T><<<Gn, kThreads, 0, st_>>>(vbuf_, dbg_idx_[1], dbg_key_[1], n);
+    IC_LAUNCHED();
+    rk::k_fourier_targets<T><<<Gn, kThreads, 0, st_>>>(keys_, binc_ + 128, event, prob_.seed,
+                                                       tbuf_, keys_, vals_, small_, n);
+    IC_LAUNCHED();
+    radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, vbits, st_);
+    sk::k_gather_u32_key<<<Gn, kThreads, 0, st_>>>(small_, vals_, keys_, n);
+    IC_LAUNCHED();
+    radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, 8, st_);
+    rk::k_fourier_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, dbg_idx_[1], tbuf_, vals_,
+                                                       static_cast<T>(n3h), n);
+    IC_LAUNCHED();
+  }
+  fft_x<T>(f, Z, Z, false, static_cast<T>(1.0 / (double)P_));
+  fft_y<T>(f, Z, false);
+  fft_c2r_z<T>(f, Z, s, T(1), nullptr, T(0));
+  return n;
+}
+
+template <typename T>
+void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfgs_info* info) {
+  if (!sv || !gv || !loss) throw ApiError(IC_ERR_INVALID_ARG, "null argument");
+  if (!counts_) throw ApiError(IC_ERR_STATE, "no observation set");
+  T* s = static_cast<T*>(sv);
+  T* g = static_cast<T*>(gv);
+  const double L = *loss;
+  const int m = prob_.lbfgs_m;
+  ic_lbfgs_info inf{};
+  // Two-loop recursion: dir = -H g with H0 = gamma I.
+  copy(g, dir_, P_);
+  const int h = static_cast<int>(hist_.size());
+  std::vector<double> alpha(h);
+  for (int i = h - 1; i >= 0; --i) {
+    const int sl = hist_[i];
+    alpha[i] = hist_rho_[sl] * dot(hist_S_ + sl * P_, dir_, P_);
+    axpy(dir_, hist_Y_ + sl * P_, -alpha[i], dir_, P_);
+  }
+  const double gamma = h ? hist_sy_[hist_.back()] / hist_yy_[hist_.back()] : 1.0;
+  if (gamma != 1.0) axpy(dir_, dir_, gamma - 1.0, dir_, P_);
+  for (int i = 0; i < h; ++i) {
+    const int sl = hist_[i];
+    const double b = hist_rho_[sl] * dot(hist_Y_ + sl * P_, dir_, P_);
+    axpy(dir_, hist_S_ + sl * P_, alpha[i] - b, dir_, P_);
+  }
+  axpy(dir_, dir_, -2.0, dir_, P_);
+  double gp = dot(g, dir_, P_);
+  if (!(gp < 0)) {
+    lbfgs_reset();
+    axpy(g, g, -2.0, dir_, P_);
+    gp = dot(g, dir_, P_);
+    inf.restarted = 1;
+  }
+  double eps = prob_.eps_max;
+  bool accepted = false;
+  ic_loss_terms t{};
+  int trial = 0;
+  for (; trial < prob_.max_trials; ++trial) {
+    axpy(s, dir_, eps, strial_, P_);
+    inf.resets = project(strial_, strial_, (uint64_t)trial, (uint64_t)it);
+    eval(strial_, gtrial_, &t);
+    inf.evaluations++;
+    if (t.loss <= L + prob_.armijo_c1 * eps * gp) {
+      accepted = true;
+      break;
+    }
+    eps *= 0.5;
+  }
+  inf.trials = accepted ? trial + 1 : trial;
+  inf.gp = gp;
+  if (!accepted) {
+    if (info) *info = inf;
+    throw ApiError(IC_ERR_LINESEARCH, "line search found no acceptable step");
+  }
+  inf.eps = eps;
+  const int sl = free_slots_.back();
+  T* Sv = hist_S_ + sl * P_;
+  T* Yv = hist_Y_ + sl * P_;
+  fk::k_sub<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(strial_, s, Sv, P_);
+  IC_LAUNCHED();
+  fk::k_sub<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(gtrial_, g, Yv, P_);
+  IC_LAUNCHED();
+  const double sy = dot(Sv, Yv, P_), ss = dot(Sv, Sv, P_), yy = dot(Yv, Yv, P_);
+  if (sy > 1e-10 * std::sqrt(ss * yy)) {
+    free_slots_.pop_back();
+    hist_.push_back(sl);
+    hist_rho_[sl] = 1.0 / sy;
+    hist_sy_[sl] = sy;
+    hist_yy_[sl] = yy;
+    if ((int)hist_.size() > m) {
+      free_slots_.push_back(hist_.front());
+      hist_.pop_front();
+    }
+    inf.stored = 1;
+  }
+  inf.history = static_cast<int32_t>(hist_.size());
+  copy(strial_, s, P_);
+  copy(gtrial_, g, P_);
+  *loss = t.loss;
+  IC_HIP(hipStreamSynchronize(st_));
+  if (info) *info = inf;
+}
+
+}  // namespace ic

@@ -1,0 +1,74 @@
+// Host interface of the LDS-staged Stockham FFT passes (gfx950).
+//
+// A 3D real transform of an n^3 cube is three axis passes: a real-to-complex
+// pass along the contiguous z axis (half-length complex FFT plus the
+// even/odd split), and complex passes along y and x over the half spectrum
+// [n][n][n/2+1] (numpy rfftn layout).  The x pass is the last forward axis
+// and the first inverse one, so k-space multipliers are applied inside it:
+// one kernel runs the forward x FFT, multiplies by m multipliers and runs m
+// inverse x FFTs (scatter), or the reverse for m inputs summed into one
+// output (gather).  Inverse passes are unnormalised; the 1/n^3 of the
+// inverse real DFT is folded into the multiplier scale.
+#pragma once
+
+#include "common.h"
+
+namespace ic {
+
+enum MulKind : int { MUL_WHITE = 1, MUL_GRAD = 2, MUL_HESS = 4 };
+
+// One k-space multiplier: scale * [w(k)] * [i k~_ga / k^2] * [k~_ha k~_hb / k^2].
+// With no kind bits it is the plain scale (the k = 0 mode kept); otherwise it
+// vanishes at k = 0.
+struct MulSpec {
+  int kinds = 0;
+  int ga = 0, ha = 0, hb = 0;
+  double scale = 1.0;
+};
+
+constexpr int kMaxMul = 9;
+
+struct MulSet {
+  int kinds[kMaxMul];
+  int ga[kMaxMul];
+  int ha[kMaxMul];
+  int hb[kMaxMul];
+  double scale[kMaxMul];
+};
+
+template <typename T>
+struct FftArgs {
+  int n = 0;                    // grid side
+  const cx<T>* tw = nullptr;    // device table exp(-2 pi i m / n), m < n
+  const T* wtab = nullptr;      // whitening multiplier indexed by |k|^2 / kf^2 (particle grid)
+  double box = 1.0;             // box side (for i k / k^2)
+  hipStream_t stream = nullptr;
+};
+
+// out = forward rfft along z of (alpha a + beta b); b may be null.
+template <typename T>
+void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out);
+
+// out = alpha * (unnormalised inverse rfft along z of in) + beta * aux (aux may be null).
+template <typename T>
+void fft_c2r_z(const FftArgs<T>& f, const cx<T>* in, T* out, T alpha, const T* aux, T beta);
+
+// In-place complex FFT along y of the half spectrum (forward or inverse, unnormalised).
+template <typename T>
+void fft_y(const FftArgs<T>& f, cx<T>* data, bool forward);
+
+// Complex FFT along x, out = scale * FFT(in); in may equal out.
+template <typename T>
+void fft_x(const FftArgs<T>& f, const cx<T>* in, cx<T>* out, bool forward, T scale);
+
+// Forward x FFT of in, then for each j < m: outs[j] = inverse x FFT of (mult_j * .).
+template <typename T>
+void fft_x_scatter(const FftArgs<T>& f, const cx<T>* in, cx<T>* const* outs,
+                   const MulSpec* specs, int m);
+
+// out = inverse x FFT of sum_j mult_j * forward x FFT of ins[j]; out may equal ins[0].
+template <typename T>
+void fft_x_gather(const FftArgs<T>& f, const cx<T>* const* ins, const MulSpec* specs, int m,
+                  cx<T>* out);
+
+}  // namespace ic

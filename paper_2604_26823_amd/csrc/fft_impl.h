@@ -1,0 +1,559 @@
+// Stockham FFT passes staged in LDS for gfx950 (64-wide wavefronts).
+//
+// Each 1D transform of length n is done by n / R_max threads ("lanes") that
+// hold R_max points in registers; a stage is one radix-R butterfly per
+// (lane, batch) with the Stockham autosort index map, so data stays in
+// natural order and every stage reads contiguous element runs.  Stages
+// exchange data through LDS; the first stage reads global memory and the
+// last one writes it, so each pass touches HBM once per element in and out.
+//
+// Strided passes (y, x) put consecutive lines of the batch on consecutive
+// threads, so every global access of a wavefront covers LINES consecutive
+// complex values (128 B in FP32); the z pass keeps lanes of one line on
+// consecutive threads because its lines are contiguous.
+#pragma once
+
+#include "fft.h"
+
+namespace ic {
+namespace fftk {
+
+// Radix plan (up to three stages) for complex length n.
+template <int n> struct Plan;
+#define IC_FFT_PLAN(N, A, B, C)                                 \
+  template <> struct Plan<N> {                                  \
+    static constexpr int R0 = A, R1 = B, R2 = C;                \
+    static constexpr int S = (B == 1) ? 1 : ((C == 1) ? 2 : 3); \
+    static constexpr int RMAX = (A > B ? (A > C ? A : C) : (B > C ? B : C)); \
+    static constexpr int TPL = N / RMAX;                        \
+  };
+IC_FFT_PLAN(2, 2, 1, 1)
+IC_FFT_PLAN(4, 4, 1, 1)
+IC_FFT_PLAN(8, 8, 1, 1)
+IC_FFT_PLAN(16, 16, 1, 1)
+IC_FFT_PLAN(32, 8, 4, 1)
+IC_FFT_PLAN(64, 8, 8, 1)
+IC_FFT_PLAN(128, 16, 8, 1)
+IC_FFT_PLAN(256, 16, 16, 1)
+IC_FFT_PLAN(512, 8, 8, 8)
+IC_FFT_PLAN(1024, 16, 8, 8)
+#undef IC_FFT_PLAN
+
+// cos and sin of 2 pi m / 16, m = 0..7.
+__device__ constexpr double kC16[8] = {1.0,
+                                       0.92387953251128675613,
+                                       0.70710678118654752440,
+                                       0.38268343236508977173,
+                                       0.0,
+                                       -0.38268343236508977173,
+                                       -0.70710678118654752440,
+                                       -0.92387953251128675613};
+__device__ constexpr double kS16[8] = {0.0,
+                                       0.38268343236508977173,
+                                       0.70710678118654752440,
+                                       0.92387953251128675613,
+                                       1.0,
+                                       0.92387953251128675613,
+                                       0.70710678118654752440,
+                                       0.38268343236508977173};
+
+// x * exp(-+ 2 pi i k / R) (forward: minus), k < R/2.
+template <typename T, int R, bool FWD>
+__device__ __forceinline__ cx<T> rot(cx<T> x, int k) {
+  if (k == 0) return x;
+  if (4 * k == R) return FWD ? mkc<T>(x.y, -x.x) : mkc<T>(-x.y, x.x);
+  const int m = k * (16 / R);
+  const T c = static_cast<T>(kC16[m]);
+  const T s = FWD ? -static_cast<T>(kS16[m]) : static_cast<T>(kS16[m]);
+  return mkc<T>(x.x * c - x.y * s, x.x * s + x.y * c);
+}
+
+// In-register DFT of length R (R a power of two <= 16), decimation in time.
+template <typename T, int R, bool FWD>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    cx<T> a = v[0];
+    v[0] = cadd<T>(a, v[1]);
+    v[1] = csub<T>(a, v[1]);
+  } else {
+    cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    dft<T, R / 2, FWD>(e);
+    dft<T, R / 2, FWD>(o);
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      cx<T> t = rot<T, R, FWD>(o[k], k);
+      v[k] = cadd<T>(e[k], t);
+      v[k + R / 2] = csub<T>(e[k], t);
+    }
+  }
+}
+
+// One Stockham stage of radix R on a length-n transform whose sub-transforms
+// have size Ns.  Butterfly j reads elements j + r n/R, twiddles them by
+// W_{Ns R}^{(j mod Ns) r} and writes (j - j mod Ns) R + j mod Ns + r Ns.
+// tw is the table exp(-2 pi i m / (n * tws)).  All reads of the stage
+// happen before the (optional) barrier and all writes after it, so a stage
+// may write the buffer it read.
+template <typename T, int n, int R, int TPL, bool FWD, class Load, class Store>
+__device__ __forceinline__ void stage(int lane, int Ns, const cx<T>* __restrict__ tw, int tws,
+                                      Load&& load, Store&& store, bool sync_before_store) {
+  constexpr int NB = n / R;
+  static_assert(NB % TPL == 0, "butterflies must divide evenly over lanes");
+  constexpr int BPT = NB / TPL;
+  cx<T> v[BPT][R];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int jb = lane + b * TPL;
+    const int k = jb & (Ns - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b][r] = load(jb + r * NB);
+    if (Ns > 1) {
+      const int step = (n / (Ns * R)) * k;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[step * r * tws];
+        if (!FWD) w.y = -w.y;
+        v[b][r] = cmul<T>(v[b][r], w);
+      }
+    }
+    dft<T, R, FWD>(v[b]);
+  }
+  if (sync_before_store) __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int jb = lane + b * TPL;
+    const int k = jb & (Ns - 1);
+    const int base = (jb - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) store(base + r * Ns, v[b][r]);
+  }
+}
+
+// Full length-n transform: first stage from load0, intermediate stages in
+// the LDS buffer buf (element e of this thread's line at buf[lidx(e)]), last
+// stage to storeL.
+template <typename T, int n, bool FWD, class Load, class Store, class LIdx>
+__device__ __forceinline__ void fft_line(int lane, cx<T>* buf, LIdx lidx,
+                                         const cx<T>* __restrict__ tw, int tws, Load&& load0,
+                                         Store&& storeL) {
+  using P = Plan<n>;
+  constexpr int TPL = P::TPL;
+  auto ld = [&](int e) { return buf[lidx(e)]; };
+  auto st = [&](int e, cx<T> v) { buf[lidx(e)] = v; };
+  if constexpr (P::S == 1) {
+    stage<T, n, P::R0, TPL, FWD>(lane, 1, tw, tws, load0, storeL, true);
+  } else if constexpr (P::S == 2) {
+    stage<T, n, P::R0, TPL, FWD>(lane, 1, tw, tws, load0, st, true);
+    __syncthreads();
+    stage<T, n, P::R1, TPL, FWD>(lane, P::R0, tw, tws, ld, storeL, true);
+  } else {
+    stage<T, n, P::R0, TPL, FWD>(lane, 1, tw, tws, load0, st, true);
+    __syncthreads();
+    stage<T, n, P::R1, TPL, FWD>(lane, P::R0, tw, tws, ld, st, true);
+    __syncthreads();
+    stage<T, n, P::R2, TPL, FWD>(lane, P::R0 * P::R1, tw, tws, ld, storeL, true);
+  }
+}
+
+// ---------------------------------------------------------------- sizing
+template <typename T, int N> struct ZCfg {
+  static constexpr int n = N / 2;
+  static constexpr int TPL = Plan<n>::TPL;
+  static constexpr int LINES0 = 256 / TPL;
+  static constexpr int LINES = LINES0 > 64 ? 64 : (LINES0 < 1 ? 1 : LINES0);
+  static constexpr int THREADS = LINES * TPL;
+  static constexpr int LS = n + 2;  // padded LDS line stride (complex)
+};
+
+template <typename T, int N> struct SCfg {  // strided C2C passes
+  static constexpr int TPL = Plan<N>::TPL;
+  static constexpr int LINES0 = sizeof(T) == 4 ? 16 : (N >= 1024 ? 4 : 8);
+  static constexpr int LINES = (N <= 16) ? 64 : LINES0;
+  static constexpr int THREADS = LINES * TPL;
+  static constexpr int LP = LINES + 1;  // padded LDS element stride
+};
+
+template <typename T, int N> struct FCfg {  // fused x passes (two LDS tiles)
+  static constexpr int TPL = Plan<N>::TPL;
+  static constexpr int LINES = (N <= 16) ? 64
+                               : (sizeof(T) == 4 ? (N <= 512 ? 16 : 8)
+                                                 : (N <= 512 ? 8 : 2));
+  static constexpr int THREADS = LINES * TPL;
+  static constexpr int LP = LINES + 1;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_table(cx<T>* dst, const cx<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ z pass R2C
+template <typename T, int N>
+__global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
+    const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
+    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines) {
+  using C = ZCfg<T, N>;
+  constexpr int n = C::n;
+  __shared__ cx<T> buf[C::LINES * C::LS];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);
+  __syncthreads();
+  const int lane = threadIdx.x % C::TPL;
+  const int l = threadIdx.x / C::TPL;
+  const int line = blockIdx.x * C::LINES + l;
+  const bool valid = line < nlines;
+  const cx<T>* ain = reinterpret_cast<const cx<T>*>(a + (size_t)line * N);
+  const cx<T>* bin = b ? reinterpret_cast<const cx<T>*>(b + (size_t)line * N) : nullptr;
+  auto load0 = [&](int e) -> cx<T> {
+    if (!valid) return mkc<T>(0, 0);
+    cx<T> v = cscale<T>(ain[e], alpha);
+    if (bin) {
+      cx<T> w = bin[e];
+      v.x += beta * w.x;
+      v.y += beta * w.y;
+    }
+    return v;
+  };
+  cx<T>* lb = buf + l * C::LS;
+  auto lidx = [&](int e) { return l * C::LS + e; };
+  auto storeL = [&](int e, cx<T> v) { lb[e] = v; };
+  fft_line<T, n, true>(lane, buf, lidx, tw, 2, load0, storeL);
+  __syncthreads();
+  if (!valid) return;
+  cx<T>* o = out + (size_t)line * (n + 1);
+  const T half = static_cast<T>(0.5);
+  for (int k = lane; k <= n; k += C::TPL) {
+    cx<T> zk = lb[k == n ? 0 : k];
+    cx<T> zc = cconj<T>(lb[k == 0 ? 0 : n - k]);
+    cx<T> e = cscale<T>(cadd<T>(zk, zc), half);
+    cx<T> d = cscale<T>(csub<T>(zk, zc), half);
+    // X[k] = E + W^k (-i D), W = exp(-2 pi i / N)
+    cx<T> mid = mkc<T>(d.y, -d.x);
+    o[k] = cadd<T>(e, cmul<T>(tw[k], mid));
+  }
+}
+
+// ------------------------------------------------------------ z pass C2R
+template <typename T, int N>
+__global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
+    const cx<T>* __restrict__ in, T* __restrict__ out, T alpha, const T* __restrict__ aux,
+    T beta, const cx<T>* __restrict__ twg, int nlines) {
+  using C = ZCfg<T, N>;
+  constexpr int n = C::n;
+  __shared__ cx<T> buf[C::LINES * C::LS];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);
+  const int lane = threadIdx.x % C::TPL;
+  const int l = threadIdx.x / C::TPL;
+  const int line = blockIdx.x * C::LINES + l;
+  const bool valid = line < nlines;
+  cx<T>* lb = buf + l * C::LS;
+  const cx<T>* src = in + (size_t)line * (n + 1);
+  for (int k = lane; k <= n; k += C::TPL) {
+    cx<T> v = valid ? src[k] : mkc<T>(0, 0);
+    if (k == 0 || k == n) v.y = 0;  // the real transform ignores these imaginary parts
+    lb[k] = v;
+  }
+  __syncthreads();
+  auto load0 = [&](int e) -> cx<T> {
+    cx<T> xk = lb[e];
+    cx<T> xc = cconj<T>(lb[n - e]);
+    cx<T> s = cadd<T>(xk, xc);
+    cx<T> d = csub<T>(xk, xc);
+    cx<T> w = cconj<T>(tw[e]);  // exp(+2 pi i e / N)
+    cx<T> wd = cmul<T>(w, d);
+    return mkc<T>(s.x - wd.y, s.y + wd.x);  // s + i w d
+  };
+  auto lidx = [&](int e) { return l * C::LS + e; };
+  cx<T>* dst = reinterpret_cast<cx<T>*>(out + (size_t)line * N);
+  const cx<T>* ax = aux ? reinterpret_cast<const cx<T>*>(aux + (size_t)line * N) : nullptr;
+  auto storeL = [&](int e, cx<T> v) {
+    if (!valid) return;
+    cx<T> r = cscale<T>(v, alpha);
+    if (ax) {
+      cx<T> u = ax[e];
+      r.x += beta * u.x;
+      r.y += beta * u.y;
+    }
+    dst[e] = r;
+  };
+  fft_line<T, n, false>(lane, buf, lidx, tw, 2, load0, storeL);
+}
+
+// ------------------------------------------------- strided C2C (y or x)
+// Line L of the batch starts at (L / group) * gstride + L % group and its
+// elements are estride apart.
+template <typename T, int N, bool FWD>
+__global__ __launch_bounds__((SCfg<T, N>::THREADS)) void k_strided(
+    const cx<T>* in, cx<T>* out, T scale, const cx<T>* __restrict__ twg, int nlines, int group,
+    long long gstride, long long estride) {
+  using C = SCfg<T, N>;
+  __shared__ cx<T> buf[N * C::LP];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);
+  __syncthreads();
+  const int l = threadIdx.x % C::LINES;
+  const int lane = threadIdx.x / C::LINES;
+  const int line = blockIdx.x * C::LINES + l;
+  const bool valid = line < nlines;
+  const long long base = (long long)(line / group) * gstride + (line % group);
+  auto load0 = [&](int e) -> cx<T> { return valid ? in[base + e * estride] : mkc<T>(0, 0); };
+  auto storeL = [&](int e, cx<T> v) {
+    if (valid) out[base + e * estride] = cscale<T>(v, scale);
+  };
+  auto lidx = [&](int e) { return e * C::LP + l; };
+  fft_line<T, N, FWD>(lane, buf, lidx, tw, 1, load0, storeL);
+}
+
+// ------------------------------------------------- k-space multipliers
+// Integer wavenumber of index i on a full axis of side N and its derivative
+// version (0 at the Nyquist index).
+__device__ __forceinline__ int wave_index(int i, int N) { return i < N / 2 ? i : i - N; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> apply_mult(cx<T> v, const MulSet& ms, int j, int n2,
+                                            const int* dk, const T* __restrict__ wtab,
+                                            T L_over_2pi) {
+  const int kinds = ms.kinds[j];
+  T f = static_cast<T>(ms.scale[j]);
+  if (kinds == 0) return cscale<T>(v, f);
+  if (n2 == 0) return mkc<T>(0, 0);
+  if (kinds & MUL_WHITE) f *= wtab[n2];
+  const T inv = static_cast<T>(1) / static_cast<T>(n2);
+  if (kinds & MUL_HESS) f *= static_cast<T>(dk[ms.ha[j]] * dk[ms.hb[j]]) * inv;
+  if (kinds & MUL_GRAD) {
+    f *= L_over_2pi * static_cast<T>(dk[ms.ga[j]]) * inv;
+    return mkc<T>(-v.y * f, v.x * f);  // i f v
+  }
+  return cscale<T>(v, f);
+}
+
+template <typename T>
+struct OutPtrs {
+  cx<T>* p[kMaxMul];
+};
+template <typename T>
+struct InPtrs {
+  const cx<T>* p[kMaxMul];
+};
+
+// Forward x FFT, then m inverse x FFTs of the multiplied spectrum.
+template <typename T, int N>
+__global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
+    const cx<T>* __restrict__ in, OutPtrs<T> outs, MulSet ms, int m,
+    const T* __restrict__ wtab, T L_over_2pi, const cx<T>* __restrict__ twg, int nlines,
+    int K) {
+  using C = FCfg<T, N>;
+  __shared__ cx<T> A[N * C::LP];
+  __shared__ cx<T> B[N * C::LP];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);
+  __syncthreads();
+  const int l = threadIdx.x % C::LINES;
+  const int lane = threadIdx.x / C::LINES;
+  const int line = blockIdx.x * C::LINES + l;
+  const bool valid = line < nlines;
+  const long long stride = (long long)nlines;  // = N * K
+  const int ky = line / K, kz = line % K;
+  const int iy = wave_index(ky, N), iz = kz;
+  const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
+  auto lidx = [&](int e) { return e * C::LP + l; };
+  auto load_in = [&](int e) -> cx<T> { return valid ? in[line + e * stride] : mkc<T>(0, 0); };
+  auto store_A = [&](int e, cx<T> v) { A[lidx(e)] = v; };
+  fft_line<T, N, true>(lane, B, lidx, tw, 1, load_in, store_A);
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    cx<T>* dst = outs.p[j];
+    auto load_m = [&](int e) -> cx<T> {
+      const int ix = wave_index(e, N);
+      const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
+      const int n2 = ix * ix + iy * iy + iz * iz;
+      return apply_mult<T>(A[lidx(e)], ms, j, n2, dk, wtab, L_over_2pi);
+    };
+    auto store_o = [&](int e, cx<T> v) {
+      if (valid) dst[line + e * stride] = v;
+    };
+    fft_line<T, N, false>(lane, B, lidx, tw, 1, load_m, store_o);
+  }
+}
+
+// Sum over m inputs of multiplier * forward x FFT, then one inverse x FFT.
+template <typename T, int N>
+__global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
+    InPtrs<T> ins, MulSet ms, int m, cx<T>* out, const T* __restrict__ wtab, T L_over_2pi,
+    const cx<T>* __restrict__ twg, int nlines, int K) {
+  using C = FCfg<T, N>;
+  __shared__ cx<T> A[N * C::LP];
+  __shared__ cx<T> B[N * C::LP];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);
+  __syncthreads();
+  const int l = threadIdx.x % C::LINES;
+  const int lane = threadIdx.x / C::LINES;
+  const int line = blockIdx.x * C::LINES + l;
+  const bool valid = line < nlines;
+  const long long stride = (long long)nlines;
+  const int ky = line / K, kz = line % K;
+  const int iy = wave_index(ky, N), iz = kz;
+  const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
+  auto lidx = [&](int e) { return e * C::LP + l; };
+  for (int j = 0; j < m; ++j) {
+    const cx<T>* src = ins.p[j];
+    auto load_in = [&](int e) -> cx<T> {
+      return valid ? src[line + e * stride] : mkc<T>(0, 0);
+    };
+    auto acc_A = [&](int e, cx<T> v) {
+      const int ix = wave_index(e, N);
+      const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
+      const int n2 = ix * ix + iy * iy + iz * iz;
+      cx<T> t = apply_mult<T>(v, ms, j, n2, dk, wtab, L_over_2pi);
+      if (j == 0)
+        A[lidx(e)] = t;
+      else
+        A[lidx(e)] = cadd<T>(A[lidx(e)], t);
+    };
+    fft_line<T, N, true>(lane, B, lidx, tw, 1, load_in, acc_A);
+  }
+  __syncthreads();
+  auto load_A = [&](int e) { return A[lidx(e)]; };
+  auto store_o = [&](int e, cx<T> v) {
+    if (valid) out[line + e * stride] = v;
+  };
+  fft_line<T, N, false>(lane, B, lidx, tw, 1, load_A, store_o);
+}
+
+// ------------------------------------------------------------ dispatch
+template <typename T, class F>
+void dispatch_n(int n, F&& f) {
+  switch (n) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    case 1024: f(std::integral_constant<int, 1024>{}); break;
+    default: throw ApiError(-2, "FFT size must be a power of two in [8, 1024]");
+  }
+}
+
+inline MulSet make_set(const MulSpec* specs, int m) {
+  if (m < 1 || m > kMaxMul) throw ApiError(-1, "multiplier count out of range");
+  MulSet s{};
+  for (int j = 0; j < m; ++j) {
+    s.kinds[j] = specs[j].kinds;
+    s.ga[j] = specs[j].ga;
+    s.ha[j] = specs[j].ha;
+    s.hb[j] = specs[j].hb;
+    s.scale[j] = specs[j].scale;
+  }
+  return s;
+}
+
+}  // namespace fftk
+
+template <typename T>
+void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out) {
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::ZCfg<T, N>;
+    const int nlines = f.n * f.n;
+    fftk::k_r2c_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
+        a, alpha, b, beta, out, f.tw, nlines);
+  });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void fft_c2r_z(const FftArgs<T>& f, const cx<T>* in, T* out, T alpha, const T* aux, T beta) {
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::ZCfg<T, N>;
+    const int nlines = f.n * f.n;
+    fftk::k_c2r_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
+        in, out, alpha, aux, beta, f.tw, nlines);
+  });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void fft_y(const FftArgs<T>& f, cx<T>* data, bool forward) {
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::SCfg<T, N>;
+    const int K = N / 2 + 1;
+    const int nlines = N * K;
+    const unsigned grid = blocks_for(nlines, C::LINES);
+    if (forward)
+      fftk::k_strided<T, N, true><<<grid, C::THREADS, 0, f.stream>>>(
+          data, data, T(1), f.tw, nlines, K, (long long)N * K, K);
+    else
+      fftk::k_strided<T, N, false><<<grid, C::THREADS, 0, f.stream>>>(
+          data, data, T(1), f.tw, nlines, K, (long long)N * K, K);
+  });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void fft_x(const FftArgs<T>& f, const cx<T>* in, cx<T>* out, bool forward, T scale) {
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::SCfg<T, N>;
+    const int K = N / 2 + 1;
+    const int nlines = N * K;
+    const unsigned grid = blocks_for(nlines, C::LINES);
+    if (forward)
+      fftk::k_strided<T, N, true><<<grid, C::THREADS, 0, f.stream>>>(
+          in, out, scale, f.tw, nlines, nlines, 0, nlines);
+    else
+      fftk::k_strided<T, N, false><<<grid, C::THREADS, 0, f.stream>>>(
+          in, out, scale, f.tw, nlines, nlines, 0, nlines);
+  });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void fft_x_scatter(const FftArgs<T>& f, const cx<T>* in, cx<T>* const* outs,
+                   const MulSpec* specs, int m) {
+  MulSet ms = fftk::make_set(specs, m);
+  fftk::OutPtrs<T> op{};
+  for (int j = 0; j < m; ++j) op.p[j] = outs[j];
+  const T l2p = static_cast<T>(f.box / (2.0 * 3.14159265358979323846));
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::FCfg<T, N>;
+    const int K = N / 2 + 1;
+    const int nlines = N * K;
+    fftk::k_x_scatter<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
+        in, op, ms, m, f.wtab, l2p, f.tw, nlines, K);
+  });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void fft_x_gather(const FftArgs<T>& f, const cx<T>* const* ins, const MulSpec* specs, int m,
+                  cx<T>* out) {
+  MulSet ms = fftk::make_set(specs, m);
+  fftk::InPtrs<T> ip{};
+  for (int j = 0; j < m; ++j) ip.p[j] = ins[j];
+  const T l2p = static_cast<T>(f.box / (2.0 * 3.14159265358979323846));
+  fftk::dispatch_n<T>(f.n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using C = fftk::FCfg<T, N>;
+    const int K = N / 2 + 1;
+    const int nlines = N * K;
+    fftk::k_x_gather<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
+        ip, ms, m, out, f.wtab, l2p, f.tw, nlines, K);
+  });
+  IC_LAUNCHED();
+}
+
+}  // namespace ic

@@ -1,0 +1,293 @@
+// Grid-wise kernels: fills, 2LPT source and assembly, the observation model
+// and loss with its adjoint seed, FP64 reductions, projection, L-BFGS
+// vector updates and the counter-based generator (gfx950).
+//
+// Every reduction accumulates in FP64 and is deterministic: blocks write
+// partial sums in a fixed order and one block adds them in a fixed order.
+#pragma once
+
+#include "common.h"
+
+namespace ic {
+namespace fk {
+
+constexpr int kRedThreads = 256;
+
+// Block-wide FP64 sum (blockDim.x == kRedThreads).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kRedThreads / 64; ++w) r += sh[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, T v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+template <typename T>
+__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// mu2 = phi_xx phi_yy + phi_xx phi_zz + phi_yy phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
+// (phi holds xx, yy, zz, xy, xz, yz, P apart).
+template <typename T>
+__global__ void k_mu2(const T* __restrict__ phi, T* __restrict__ mu, long long P) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T xx = phi[i], yy = phi[P + i], zz = phi[2 * P + i];
+    const T xy = phi[3 * P + i], xz = phi[4 * P + i], yz = phi[5 * P + i];
+    mu[i] = xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz;
+  }
+}
+
+// In place: phi <- phi_bar given mu2_bar (d mu2 / d phi_ii = sum of the other
+// two diagonal terms, d mu2 / d phi_ij = -2 phi_ij).
+template <typename T>
+__global__ void k_phi_bar(T* __restrict__ phi, const T* __restrict__ mub, long long P) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T m = mub[i];
+    const T xx = phi[i], yy = phi[P + i], zz = phi[2 * P + i];
+    phi[i] = m * (yy + zz);
+    phi[P + i] = m * (xx + zz);
+    phi[2 * P + i] = m * (xx + yy);
+    phi[3 * P + i] *= T(-2) * m;
+    phi[4 * P + i] *= T(-2) * m;
+    phi[5 * P + i] *= T(-2) * m;
+  }
+}
+
+// In place: d <- D1 Psi1 + D2 Psi2, p <- a^2 E (f1 D1 Psi1 + f2 D2 Psi2), with
+// Psi1 held in d and Psi2 in p on entry ([3][P] each).
+template <typename T>
+__global__ void k_lpt_assemble(T* __restrict__ d, T* __restrict__ p, T cd1, T cd2, T cp1, T cp2,
+                               long long n3) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T psi1 = d[i], psi2 = p[i];
+    d[i] = cd1 * psi1 + cd2 * psi2;
+    p[i] = cp1 * psi1 + cp2 * psi2;
+  }
+}
+
+// Observation model and loss on the data grid.  delta = rho - 1 (one particle
+// per data cell on average); lambda = nbar R (1 + b delta); masked cells
+// (R >= r_min) add (N - lambda)^2 / (nbar R) to chi^2 and get the adjoint
+// seed b nbar R (lambda - N) / (nbar R).  Per-block FP64 partial sums of
+// chi^2, |s|^2 and the masked-cell count go to part[3 * block + k].
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_loss(
+    const T* __restrict__ rho, const int* __restrict__ counts, const T* __restrict__ R,
+    const T* __restrict__ s, T nbar, T bias, T r_min, T* __restrict__ seed,
+    T* __restrict__ delta_out, T* __restrict__ lambda_out, double* __restrict__ part,
+    long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  double chi = 0, ss = 0, cnt = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T delta = rho[i] - T(1);
+    T sd = T(0);
+    if (delta_out) delta_out[i] = delta;
+    if (R) {
+      const T r = R[i];
+      const T lam = nbar * r * (T(1) + bias * delta);
+      if (lambda_out) lambda_out[i] = lam;
+      if (r >= r_min) {
+        const T var = nbar * r;
+        const double res = static_cast<double>(counts[i]) - static_cast<double>(lam);
+        chi += res * res / static_cast<double>(var);
+        cnt += 1.0;
+        sd = bias * nbar * r * (lam - static_cast<T>(counts[i])) / var;
+      }
+    }
+    if (seed) seed[i] = sd;
+    if (s) {
+      const double v = static_cast<double>(s[i]);
+      ss += v * v;
+    }
+  }
+  chi = block_sum(chi, sh);
+  ss = block_sum(ss, sh);
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = chi;
+    part[3 * blockIdx.x + 1] = ss;
+    part[3 * blockIdx.x + 2] = cnt;
+  }
+}
+
+// out[k] = sum_b part[stride * b + k] for k < stride (one block; fixed order).
+static __global__ __launch_bounds__(kRedThreads) void k_reduce_parts(const double* __restrict__ part,
+                                                              int nblocks, int stride,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  for (int k = 0; k < stride; ++k) {
+    double v = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[stride * b + k];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[k] = v;
+  }
+}
+
+// Partial sums of a . b (b may be null: sum of a) and of (a - shift)^2 with
+// shift read from device memory (may be null).
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_dot(const T* __restrict__ a,
+                                                     const T* __restrict__ b,
+                                                     double* __restrict__ part, long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double x = static_cast<double>(a[i]);
+    acc += b ? x * static_cast<double>(b[i]) : x;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Partial sums of (x - mean)^2, mean = sum[0] / n read from device memory.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_centered_sq(const T* __restrict__ a,
+                                                             const double* __restrict__ sum,
+                                                             double* __restrict__ part,
+                                                             long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  const double mean = sum[0] / static_cast<double>(n);
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double x = static_cast<double>(a[i]) - mean;
+    acc += x * x;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// y = a + alpha b (alpha FP64 on the host, applied in T); y may alias a or b.
+template <typename T>
+__global__ void k_axpy(const T* a, const T* b, T alpha, T* y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = a[i] + alpha * b[i];
+}
+
+// y = a - b.
+template <typename T>
+__global__ void k_sub(const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ y,
+                      long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = a[i] - b[i];
+}
+
+// ------------------------------------------------------------ Philox4x64-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two
+// 64x64->128 multiplications with the Weyl key schedule.
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                               uint64_t c3, uint64_t k0) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t k1 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  U64x4 r;
+  r.v[0] = c0;
+  r.v[1] = c1;
+  r.v[2] = c2;
+  r.v[3] = c3;
+  return r;
+}
+
+__device__ __forceinline__ double unit_open(uint64_t w) {
+  return (static_cast<double>(w >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// kind 0: sqrt(-2 ln u0) cos(2 pi u1); kind 1: sqrt(-ln u0).
+__device__ __forceinline__ double philox_draw(int kind, uint64_t j, uint64_t sub, uint64_t stream,
+                                              uint64_t event, uint64_t seed) {
+  U64x4 w = philox4x64_10(j, sub, stream, event, seed);
+  const double u0 = unit_open(w.v[0]);
+  if (kind == 1) return sqrt(-log(u0));
+  const double u1 = unit_open(w.v[1]);
+  return sqrt(-2.0 * log(u0)) * cospi(2.0 * u1);
+}
+
+template <typename T>
+__global__ void k_philox(int kind, uint64_t sub, uint64_t stream, uint64_t event, uint64_t seed,
+                         T* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = static_cast<T>(philox_draw(kind, (uint64_t)i, sub, stream, event, seed));
+}
+
+// Projection: out = (x - mean) / std with mean = sums[0]/n and
+// std = sqrt(sums[1]/n); |out| > s_th is replaced by the reset draw of that
+// element.  The reset count goes to part[block].
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_project(
+    const T* __restrict__ x, const double* __restrict__ sum, const double* __restrict__ sq,
+    T s_th, uint64_t trial, uint64_t event, uint64_t seed, T* __restrict__ out,
+    double* __restrict__ part, long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  const double mean = sum[0] / static_cast<double>(n);
+  const double sd = sqrt(sq[0] / static_cast<double>(n));
+  double resets = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    T z = static_cast<T>((static_cast<double>(x[i]) - mean) / sd);
+    if (fabs(z) > s_th) {
+      z = static_cast<T>(philox_draw(0, (uint64_t)i, trial, 1, event, seed));
+      resets += 1.0;
+    }
+    out[i] = z;
+  }
+  resets = block_sum(resets, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = resets;
+}
+
+// Non-finite check: part[block] = count of non-finite values.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_count_nonfinite(const T* __restrict__ x,
+                                                                 double* __restrict__ part,
+                                                                 long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  double bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) bad += 1.0;
+  bad = block_sum(bad, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = bad;
+}
+
+}  // namespace fk
+}  // namespace ic

@@ -1,0 +1,358 @@
+// Particle kernels: cloud-in-cell paint and readout, the fused kick-drift-
+// paint step, redshift-space distortion with the data-grid paint, and their
+// adjoints (gfx950).
+//
+// Particles are lattice points q_n = n dq plus a displacement d_n stored in
+// structure-of-arrays form [3][P] in lattice order, so consecutive threads
+// hold spatially adjacent particles and their CIC stencils touch adjacent
+// cells (coalesced gathers, clustered atomics).  The cell index is split into
+// the exact integer lattice part (n * ratio) and floor(d / cell), which keeps
+// FP32 positions accurate to the displacement's own rounding.
+#pragma once
+
+#include "common.h"
+
+namespace ic {
+namespace pk {
+
+template <typename T>
+struct Stencil {
+  int i0[3];
+  T t[3];
+};
+
+// Lattice coordinates of particle index n on a side-np lattice (np = 2^lp).
+__device__ __forceinline__ void lattice(long long n, int lp, int idx[3]) {
+  const int mask = (1 << lp) - 1;
+  idx[2] = static_cast<int>(n & mask);
+  idx[1] = static_cast<int>((n >> lp) & mask);
+  idx[0] = static_cast<int>(n >> (2 * lp));
+}
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> stencil(const int idx[3], int ratio, const T dsp[3],
+                                              T inv_cell) {
+  Stencil<T> s;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T u = dsp[a] * inv_cell;
+    const T f = floor(u);
+    s.i0[a] = idx[a] * ratio + static_cast<int>(f);
+    s.t[a] = u - f;
+  }
+  return s;
+}
+
+__device__ __forceinline__ long long cell_index(const int c[3], int mask, int lm) {
+  return ((long long)(c[0] & mask) << (2 * lm)) | ((long long)(c[1] & mask) << lm) |
+         (long long)(c[2] & mask);
+}
+
+// Geometry of one grid the particles are painted to or read from.
+template <typename T>
+struct Grid {
+  int lm;      // log2 of the grid side
+  int ratio;   // grid cells per lattice spacing (1 or 2)
+  T inv_cell;  // grid side / box
+};
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Calls f(cell, w, dw0, dw1, dw2) for the 8 CIC corners, where w is the
+// weight and dwa its derivative along axis a in units of 1/cell.
+template <typename T, class F>
+__device__ __forceinline__ void for_corners(const Stencil<T>& s, int lm, F&& f) {
+  const int mask = (1 << lm) - 1;
+#pragma unroll
+  for (int ox = 0; ox < 2; ++ox) {
+    const T wx = ox ? s.t[0] : T(1) - s.t[0];
+    const T gx = ox ? T(1) : T(-1);
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      const T wy = oy ? s.t[1] : T(1) - s.t[1];
+      const T gy = oy ? T(1) : T(-1);
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz) {
+        const T wz = oz ? s.t[2] : T(1) - s.t[2];
+        const T gz = oz ? T(1) : T(-1);
+        const int c[3] = {s.i0[0] + ox, s.i0[1] + oy, s.i0[2] + oz};
+        f(cell_index(c, mask, lm), wx * wy * wz, gx * wy * wz, wx * gy * wz, wx * wy * gz);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load3(const T* __restrict__ v, long long P, long long n, T out[3]) {
+  out[0] = v[n];
+  out[1] = v[P + n];
+  out[2] = v[2 * P + n];
+}
+
+// rho(c) += sum_n W(q_n + d_n - c).
+template <typename T>
+__global__ __launch_bounds__(256) void k_paint(const T* __restrict__ d, long long P, int lp,
+                                               Grid<T> g, T* __restrict__ rho) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3];
+    load3(d, P, n, dsp);
+    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell);
+    for_corners(s, g.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
+  }
+}
+
+// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), j = 0..2 (three meshes
+// M apart).
+template <typename T>
+__global__ __launch_bounds__(256) void k_paint_vec(const T* __restrict__ d,
+                                                   const T* __restrict__ v, T coef, long long P,
+                                                   int lp, Grid<T> g, T* __restrict__ out,
+                                                   long long M) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], vv[3];
+    load3(d, P, n, dsp);
+    load3(v, P, n, vv);
+    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell);
+    const T v0 = coef * vv[0], v1 = coef * vv[1], v2 = coef * vv[2];
+    for_corners(s, g.lm, [&](long long c, T w, T, T, T) {
+      atomic_add(out + c, w * v0);
+      atomic_add(out + M + c, w * v1);
+      atomic_add(out + 2 * M + c, w * v2);
+    });
+  }
+}
+
+// Readout of the three force meshes at particle positions: F_j = sum W g_j.
+template <typename T>
+__device__ __forceinline__ void readout3(const Stencil<T>& s, int lm, const T* __restrict__ g,
+                                         long long M, T F[3]) {
+  F[0] = F[1] = F[2] = T(0);
+  for_corners(s, lm, [&](long long c, T w, T, T, T) {
+    F[0] += w * g[c];
+    F[1] += w * g[M + c];
+    F[2] += w * g[2 * M + c];
+  });
+}
+
+// Fused step: readout of g at d_cur, kick p += kick F; if dout: drift
+// d_next = d_cur + drift p and paint rho at d_next.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pm_step(const T* __restrict__ dcur, T* __restrict__ p,
+                                                 const T* __restrict__ g, long long M, T kick,
+                                                 T drift, T* __restrict__ dnext,
+                                                 T* __restrict__ rho, long long P, int lp,
+                                                 Grid<T> gr) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], mom[3], F[3];
+    load3(dcur, P, n, dsp);
+    load3(p, P, n, mom);
+    Stencil<T> s = stencil(idx, gr.ratio, dsp, gr.inv_cell);
+    readout3(s, gr.lm, g, M, F);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mom[a] += kick * F[a];
+      p[a * P + n] = mom[a];
+    }
+    if (dnext) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        dsp[a] += drift * mom[a];
+        dnext[a * P + n] = dsp[a];
+      }
+      Stencil<T> s2 = stencil(idx, gr.ratio, dsp, gr.inv_cell);
+      for_corners(s2, gr.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
+    }
+  }
+}
+
+// Redshift-space displacement.  mode 1: shift c p_z along z; mode 2: shift
+// c (p . u) u with u the unit vector from the observer to the wrapped
+// position; r = 0 gives no shift.
+template <typename T>
+struct Rsd {
+  int mode;
+  T c;
+  T box;
+  T dq;
+  T obs[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void los(const Rsd<T>& r, const int idx[3], const T dsp[3], T u[3],
+                                    T& dist) {
+  T rr = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T x = static_cast<T>(idx[a]) * r.dq + dsp[a];
+    const T y = x - r.box * floor(x / r.box);
+    u[a] = y - r.obs[a];
+    rr += u[a] * u[a];
+  }
+  dist = sqrt(rr);
+  const T inv = dist > T(0) ? T(1) / dist : T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] *= inv;
+}
+
+template <typename T>
+__device__ __forceinline__ void rsd_shift(const Rsd<T>& r, const int idx[3], const T dsp[3],
+                                          const T mom[3], T out[3]) {
+  out[0] = dsp[0];
+  out[1] = dsp[1];
+  out[2] = dsp[2];
+  if (r.mode == 1) {
+    out[2] += r.c * mom[2];
+  } else if (r.mode == 2) {
+    T u[3], dist;
+    los(r, idx, dsp, u, dist);
+    const T pu = r.c * (mom[0] * u[0] + mom[1] * u[1] + mom[2] * u[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] += pu * u[a];
+  }
+}
+
+// Last kick (readout of g at d), then RSD and the data-grid paint.
+template <typename T>
+__global__ __launch_bounds__(256) void k_final(const T* __restrict__ d, T* __restrict__ p,
+                                               const T* __restrict__ g, long long M, T kick,
+                                               Grid<T> gm, Rsd<T> rsd, Grid<T> gd,
+                                               T* __restrict__ rho_d, long long P, int lp) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], mom[3], F[3], ds[3];
+    load3(d, P, n, dsp);
+    load3(p, P, n, mom);
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    readout3(s, gm.lm, g, M, F);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mom[a] += kick * F[a];
+      p[a * P + n] = mom[a];
+    }
+    rsd_shift(rsd, idx, dsp, mom, ds);
+    Stencil<T> s2 = stencil(idx, gd.ratio, ds, gd.inv_cell);
+    for_corners(s2, gd.lm, [&](long long c, T w, T, T, T) { atomic_add(rho_d + c, w); });
+  }
+}
+
+// Adjoint of the RSD + data paint: x_bar_s = sum_c rho_bar(c) grad W(x_s - c),
+// then the transpose of the RSD map; writes d_bar and p_bar.
+template <typename T>
+__global__ __launch_bounds__(256) void k_data_adjoint(const T* __restrict__ d,
+                                                      const T* __restrict__ p, Rsd<T> rsd,
+                                                      Grid<T> gd, const T* __restrict__ rho_bar,
+                                                      T* __restrict__ dbar, T* __restrict__ pbar,
+                                                      long long P, int lp) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], mom[3], ds[3];
+    load3(d, P, n, dsp);
+    load3(p, P, n, mom);
+    rsd_shift(rsd, idx, dsp, mom, ds);
+    Stencil<T> s = stencil(idx, gd.ratio, ds, gd.inv_cell);
+    T xb[3] = {0, 0, 0};
+    for_corners(s, gd.lm, [&](long long c, T, T d0, T d1, T d2) {
+      const T r = rho_bar[c];
+      xb[0] += d0 * r;
+      xb[1] += d1 * r;
+      xb[2] += d2 * r;
+    });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xb[a] *= gd.inv_cell;
+    T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
+    if (rsd.mode == 1) {
+      pb[2] = rsd.c * xb[2];
+    } else if (rsd.mode == 2) {
+      T u[3], dist;
+      los(rsd, idx, dsp, u, dist);
+      const T ux = u[0] * xb[0] + u[1] * xb[1] + u[2] * xb[2];
+      const T up = u[0] * mom[0] + u[1] * mom[1] + u[2] * mom[2];
+      const T cr = dist > T(0) ? rsd.c / dist : T(0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T perp_p = mom[a] - up * u[a];
+        const T perp_x = xb[a] - ux * u[a];
+        db[a] += cr * (ux * perp_p + up * perp_x);
+        pb[a] = rsd.c * ux * u[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dbar[a * P + n] = db[a];
+      pbar[a * P + n] = pb[a];
+    }
+  }
+}
+
+// Position cotangent of one force evaluation with cotangent v = coef p_bar:
+// d_bar += sum_c grad W(x - c) [sum_j v_j g_j(c) + rho_bar(c)]; then, when
+// drift != 0, the drift adjoint p_bar += drift d_bar.
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_adjoint(
+    const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
+    const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
+    int lp, Grid<T> gm) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], pb[3], db[3];
+    load3(d, P, n, dsp);
+    load3(pbar, P, n, pb);
+    load3(dbar, P, n, db);
+    const T v0 = coef * pb[0], v1 = coef * pb[1], v2 = coef * pb[2];
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    T xb[3] = {0, 0, 0};
+    for_corners(s, gm.lm, [&](long long c, T, T d0, T d1, T d2) {
+      const T h = v0 * g[c] + v1 * g[M + c] + v2 * g[2 * M + c] + rho_bar[c];
+      xb[0] += d0 * h;
+      xb[1] += d1 * h;
+      xb[2] += d2 * h;
+    });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      db[a] += xb[a] * gm.inv_cell;
+      dbar[a * P + n] = db[a];
+      if (drift != T(0)) pbar[a * P + n] = pb[a] + drift * db[a];
+    }
+  }
+}
+
+// Position cotangent of the plain readout F = sum W m: x_bar = v . grad (used
+// by the single-stage readout check).
+template <typename T>
+__global__ __launch_bounds__(256) void k_readout(const T* __restrict__ d, const T* __restrict__ g,
+                                                 long long M, T* __restrict__ F, long long P,
+                                                 int lp, Grid<T> gm) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
+       n += (long long)gridDim.x * blockDim.x) {
+    int idx[3];
+    lattice(n, lp, idx);
+    T dsp[3], f[3];
+    load3(d, P, n, dsp);
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    readout3(s, gm.lm, g, M, f);
+    F[n] = f[0];
+    F[P + n] = f[1];
+    F[2 * P + n] = f[2];
+  }
+}
+
+}  // namespace pk
+}  // namespace ic

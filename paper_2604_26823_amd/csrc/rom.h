@@ -1,0 +1,155 @@
+// Rank-order matching kernels (paper section 2.3.2): key construction for
+// the real-space set (cells with R >= r_min) and for the Fourier-space k
+// bins, target draws, and the scatter of sorted targets (gfx950).
+#pragma once
+
+#include "common.h"
+#include "fields.h"
+#include "sort.h"
+
+namespace ic {
+namespace rk {
+
+// Real space: descending value key for every cell; second key 0 on the
+// matched set (R >= r_min), 1 elsewhere, so the matched cells sort first.
+template <typename T>
+__global__ void k_real_keys(const T* __restrict__ s, const T* __restrict__ R, T r_min,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            uint32_t* __restrict__ second, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    keys[i] = sk::descending_key<T>(s[i]);
+    vals[i] = static_cast<uint32_t>(i);
+    second[i] = R[i] >= r_min ? 0u : 1u;
+  }
+}
+
+// out[j] = src[idx[j]] for j < n.
+template <typename T>
+__global__ void k_gather(const T* __restrict__ src, const uint32_t* __restrict__ idx,
+                         T* __restrict__ out, long long n) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x)
+    out[j] = src[idx[j]];
+}
+
+// Targets of the real-space set and their descending keys: N(0,1) draw j.
+template <typename T>
+__global__ void k_real_targets(uint64_t event, uint64_t seed, T* __restrict__ tau,
+                               uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                               long long n) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    const T v = static_cast<T>(fk::philox_draw(0, (uint64_t)j, 0, 2, event, seed));
+    tau[j] = v;
+    keys[j] = sk::descending_key<T>(v);
+    vals[j] = static_cast<uint32_t>(j);
+  }
+}
+
+// s[idx[j]] = tau[order[j]] for j < n: the j-th largest value gets the j-th
+// largest target.
+template <typename T>
+__global__ void k_scatter_sorted(T* __restrict__ s, const uint32_t* __restrict__ idx,
+                                 const T* __restrict__ tau, const uint32_t* __restrict__ order,
+                                 long long n) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x)
+    s[idx[j]] = tau[order[j]];
+}
+
+// Fourier space: for every half-spectrum mode f = (kx n + ky)(n/2+1) + kz,
+// amplitude |z| = |Z_f| * scale, descending key, and second key = bin for
+// matched modes (independent, |k| >= k_min) or 255.
+template <typename T>
+__global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, T scale, double kf, double kmin,
+                            double dk, int nbins, T* __restrict__ amp,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            uint32_t* __restrict__ second, long long H) {
+  const int K = n / 2 + 1;
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < H;
+       f += (long long)gridDim.x * blockDim.x) {
+    const int kz = static_cast<int>(f % K);
+    const long long r = f / K;
+    const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
+    const cx<T> z = Z[f];
+    const T a = sqrt(z.x * z.x + z.y * z.y) * scale;
+    amp[f] = a;
+    keys[f] = sk::descending_key<T>(a);
+    vals[f] = static_cast<uint32_t>(f);
+    bool independent = true;
+    if (kz == 0 || kz == n / 2) {
+      const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
+      const long long conj = ((long long)cx_ * n + cy) * K + kz;
+      independent = f < conj;
+    }
+    const int ix = kx < n / 2 ? kx : kx - n;
+    const int iy = ky < n / 2 ? ky : ky - n;
+    const double k = kf * sqrt((double)(ix * ix + iy * iy + kz * kz));
+    uint32_t bin = 255u;
+    if (independent && k >= kmin) {
+      int b = static_cast<int>(floor((k - kmin) / dk));
+      bin = static_cast<uint32_t>(b < nbins - 1 ? b : nbins - 1);
+    }
+    second[f] = bin;
+  }
+}
+
+// Counts of each bin over the sorted second keys (bins < 255).
+static __global__ void k_bin_count(const uint64_t* __restrict__ bins, uint32_t* __restrict__ counts,
+                            long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const uint64_t b = bins[i];
+    if (b < 255) atomicAdd(&counts[b], 1u);
+  }
+}
+
+// Rayleigh target of sorted position i: bin b = bins[i], index within the
+// bin j = i - start[b]; second key of the target sort is the bin.
+template <typename T>
+__global__ void k_fourier_targets(const uint64_t* __restrict__ bins,
+                                  const uint32_t* __restrict__ start, uint64_t event,
+                                  uint64_t seed, T* __restrict__ tau,
+                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                  uint32_t* __restrict__ second, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const uint32_t b = static_cast<uint32_t>(bins[i]);
+    const uint64_t j = (uint64_t)(i - start[b]);
+    const T v = static_cast<T>(fk::philox_draw(1, j, b, 3, event, seed));
+    tau[i] = v;
+    keys[i] = sk::descending_key<T>(v);
+    vals[i] = static_cast<uint32_t>(i);
+    second[i] = b;
+  }
+}
+
+// Z_f <- tau * unscale * Z_f / |Z_f| (tau * unscale when Z_f = 0) for the
+// matched mode f = idx[i], with the target tau[order[i]]; modes of the kz = 0
+// and kz = n/2 planes also set their conjugate partner.
+template <typename T>
+__global__ void k_fourier_scatter(cx<T>* __restrict__ Z, int n, const uint32_t* __restrict__ idx,
+                                  const T* __restrict__ tau, const uint32_t* __restrict__ order,
+                                  T unscale, long long cnt) {
+  const int K = n / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long f = idx[i];
+    const T t = tau[order[i]] * unscale;
+    const cx<T> z = Z[f];
+    const T a = sqrt(z.x * z.x + z.y * z.y);
+    const cx<T> v = a > T(0) ? mkc<T>(z.x * (t / a), z.y * (t / a)) : mkc<T>(t, T(0));
+    Z[f] = v;
+    const int kz = static_cast<int>(f % K);
+    if (kz == 0 || kz == n / 2) {
+      const long long r = f / K;
+      const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
+      const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
+      Z[((long long)cx_ * n + cy) * K + kz] = mkc<T>(v.x, -v.y);
+    }
+  }
+}
+
+}  // namespace rk
+}  // namespace ic

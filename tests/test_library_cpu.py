@@ -1,0 +1,92 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+validates problems, sizes workspaces and computes the same FP64 cosmology
+coefficients as the oracle.  No device work is started here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import cosmology
+from paper_2604_26823_amd import _lib, api, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2604_26823_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    names = []
+    for h in ("ic_api.h", "ic_ops.h"):
+        with open(os.path.join(ROOT, "include", h)) as f:
+            text = f.read()
+        names += re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(ic_\w+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_abi_version_and_defaults(lib):
+    assert lib.ic_abi_version() == 1
+    p = _lib.IcProblem()
+    lib.ic_problem_defaults(ctypes.byref(p))
+    assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
+    assert p.eps_max == 1.0 and p.a_init == 0.1 and p.lbfgs_m == 10
+
+
+def _size(lib, cfg, prec=_lib.IC_F32):
+    p = api.make_problem(cfg)
+    size = ctypes.c_size_t()
+    rc = lib.ic_workspace_size(ctypes.byref(p), prec, ctypes.byref(size))
+    return rc, size.value
+
+
+def test_workspace_sizes_and_validation(lib):
+    rc, b32 = _size(lib, inputs.config(3))
+    assert rc == 0
+    rc, b64 = _size(lib, inputs.config(3), _lib.IC_F64)
+    assert rc == 0 and 1.9 < b64 / b32 < 2.1
+    # 256^3 FP32 fits comfortably in one MI355X's 288 GB
+    assert 4e9 < b32 < 2e10
+    for bad in [dict(n_part=48), dict(n_part=1024, n_mesh=1024), dict(n_mesh=96)]:
+        cfg = inputs.config(1, **bad)
+        rc, _ = _size(lib, cfg)
+        assert rc == -2, bad
+        assert b"n_" in lib.ic_last_error(None)
+    rc, _ = _size(lib, inputs.config(1, n_steps=0))
+    assert rc == -1
+    rc, _ = _size(lib, inputs.config(1), 7)
+    assert rc == -1
+
+
+@pytest.mark.parametrize("om,steps", [(0.3, 5), (0.3, 10), (1.0, 4)])
+def test_host_coefficients_match_oracle(lib, om, steps):
+    cfg = inputs.config(1, omega_m=om, n_steps=steps)
+    p = api.make_problem(cfg)
+    out = (ctypes.c_double * (7 + 3 * steps))()
+    assert lib.ic_host_coefficients(ctypes.byref(p), out, len(out)) == 0
+    got = np.array(out[:])
+    co = cosmology.fastpm_coefficients(om, 0.1, 1.0, steps)
+    pk = cosmology.PowerSpectrum(om, 0.7, 0.96, 0.8)
+    ref = np.concatenate([[co["D1_init"], co["f1_init"], co["D2_init"], co["f2_init"],
+                           co["E_init"], co["rsd_factor"], pk.amplitude],
+                          co["Dr"], co["K1"], co["K2"]])
+    assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-10
+
+
+def test_product_path_fails_loudly_without_library(tmp_path):
+    with pytest.raises(_lib.NativeLibraryMissing):
+        _lib.load(str(tmp_path / "missing.so"))
