@@ -1,0 +1,269 @@
+"""Benchmark of the reconstruction hot path on one MI355X.
+
+One step is one projected L-BFGS iteration of the method (projection of
+s + eps p, loss + gradient evaluations of the line search, two-loop
+recursion with FP64 dot products, history update), with the rank-order
+matching event (projection + real-space + Fourier-space matching, history
+reset, re-evaluation) every ``rom_every`` iterations, on the 256^3 survey-
+shaped synthetic workload (c3).  The metric is gradient evaluations per
+second: all loss + gradient evaluations made in the K timed steps divided by
+their wall time, inputs already resident in HBM.
+
+Also reported: the same loop with the FP64 instantiation of the kernels, the
+per-kernel HIP-event timing of a separate K-step pass (dominant kernel's
+algorithmic HBM bandwidth against the 8 TB/s peak), and the FP64 CPU oracle's
+rate estimated from a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
+                       [--no-fp64] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = {
+    1: "c1: 32^3 particles and mesh, 256 Mpc/h, 5 KDK steps, z-axis RSD, half-box mask",
+    2: "c2: 128^3 particles and mesh, 512 Mpc/h, 10 KDK steps, radial RSD, 40x40 deg cone, "
+       "~1e6 galaxies",
+    3: "c3: 256^3 particles on a 256^3 mesh, 1000 Mpc/h, 10 KDK steps, radial RSD, 40x40 deg "
+       "cone, r^2 exp(-(r/300)^1.5) selection, ~8e6 galaxies",
+    4: "c4: 256^3 particles on a 512^3 mesh, 1000 Mpc/h, 20 KDK steps",
+    5: "c5: 512^3 particles on a 1024^3 mesh, 2000 Mpc/h, 20 KDK steps",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def setup(cfg, prec, counts=None, s_start=None):
+    import torch
+
+    from paper_2604_26823_amd import _lib, inputs
+    from paper_2604_26823_amd.api import Context
+
+    ctx = Context(cfg, prec, "cuda:0")
+    R = inputs.response_field(cfg)
+    resp = torch.tensor(R, dtype=ctx.dtype, device=ctx.device)
+    if counts is None:
+        # Mock data: the truth white noise through this library's forward model,
+        # Poisson-sampled on the host from the seeded generator.
+        sd = inputs.seeds(cfg["id"])
+        s_true = torch.tensor(inputs.white_noise(cfg["n_part"], sd["truth"]), dtype=ctx.dtype,
+                              device=ctx.device)
+        dummy = torch.zeros(ctx.grid, dtype=torch.int32, device=ctx.device)
+        ctx.set_observation(dummy, resp)
+        lam = ctx.forward(s_true, delta=False, lam=True)["lambda"].double().cpu().numpy()
+        counts = inputs.poisson_counts(lam, R, cfg["r_min"], sd["counts"])
+        s_start = inputs.white_noise(cfg["n_part"], sd["start"])
+    ctx.set_observation(torch.tensor(counts, dtype=torch.int32, device=ctx.device), resp)
+    s = torch.tensor(s_start, dtype=ctx.dtype, device=ctx.device)
+    ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+    return ctx, s, counts, s_start
+
+
+def run_steps(ctx, s, g, L, first, k, rom_every):
+    """k L-BFGS iterations starting at iteration index first; returns
+    (L, evaluations, rom events)."""
+    from paper_2604_26823_amd import _lib
+    evals = roms = 0
+    for it in range(first, first + k):
+        L, info = ctx.lbfgs_step(s, g, L, it)
+        evals += info["evaluations"]
+        if rom_every and (it + 1) % rom_every == 0:
+            ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL | _lib.IC_ROM_FOURIER,
+                                  event=it + 1)
+            ctx.lbfgs_reset()
+            L, _, _ = ctx.loss_and_grad(s, g)
+            evals += 1
+            roms += 1
+    return L, evals, roms
+
+
+def timed_loop(ctx, s, steps, warmup, rom_every):
+    import torch
+    L, g, _ = ctx.loss_and_grad(s)
+    L, _, _ = run_steps(ctx, s, g, L, 0, warmup, rom_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L, evals, roms = run_steps(ctx, s, g, L, warmup, steps, rom_every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dict(seconds=dt, evals=evals, roms=roms, loss=L, g=g)
+
+
+def kernel_table(ctx, s, g, L, first, steps, rom_every):
+    ctx.timing(True)
+    run_steps(ctx, s, g, L, first, steps, rom_every)
+    rows = ctx.timing_report()
+    ctx.timing(False)
+    return rows
+
+
+def roofline(rows):
+    """Dominant kernel (largest total time) and its algorithmic bandwidth."""
+    tot = sum(r["ms"] for r in rows)
+    dom = max(rows, key=lambda r: r["ms"])
+    avg_ms = dom["ms"] / dom["count"]
+    gbs = dom["bytes"] / (avg_ms * 1e-3) / 1e9
+    table = {r["name"]: dict(launches=r["count"], total_ms=round(r["ms"], 3),
+                             avg_us=round(1e3 * r["ms"] / r["count"], 2),
+                             gbs=round(r["bytes"] / (r["ms"] / r["count"] * 1e-3) / 1e9, 1)
+                             if r["bytes"] > 0 else None,
+                             share=round(r["ms"] / tot, 4)) for r in rows}
+    return dict(bound="hbm", kernel=dom["name"], achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                avg_us=round(1e3 * avg_ms, 2), bytes_per_launch=dom["bytes"]), table
+
+
+def cpu_baseline(cfg):
+    """FP64 oracle rate at this workload, estimated from a bounded sample.
+
+    The oracle's evaluation cost is dominated by its CIC passes, whose cost is
+    linear in the particle count.  Sample: one CIC paint and one CIC readout
+    of the oracle on this workload's particle set; scale: the ratio of a full
+    oracle loss + gradient evaluation to that same paint + readout pair,
+    measured on the same configuration at 64^3 particles."""
+    import numpy as np
+
+    from oracle import cic
+    from oracle.model import Model, Problem
+    from paper_2604_26823_amd import inputs
+
+    def model_for(c):
+        fields = {k: c[k] for k in Problem.__dataclass_fields__ if k in c}
+        return Model(Problem(**fields))
+
+    def pair_time(mdl, d):
+        x = mdl.q + d
+        t0 = time.perf_counter()
+        rho = cic.paint(x, mdl.p.n_mesh, mdl.dm)
+        cic.readout(x, rho, mdl.dm)
+        return time.perf_counter() - t0
+
+    small = dict(cfg, n_part=64, n_mesh=64 * cfg["n_mesh"] // cfg["n_part"],
+                 box=cfg["box"] * 64 / cfg["n_part"])
+    R = inputs.response_field(small)
+    small["nbar"] = inputs.nbar_for(small, R)
+    ms = model_for(small)
+    s = inputs.white_noise(64, 7)
+    N = inputs.poisson_counts(ms.observe(ms.forward(s), R), R, small["r_min"], 8)
+    t0 = time.perf_counter()
+    ms.loss_and_grad(s, N, R)
+    t_eval_small = time.perf_counter() - t0
+    d_small, _, _ = ms.lpt(s)
+    ratio = t_eval_small / pair_time(ms, d_small * 10)
+
+    big = model_for(cfg)
+    rng = np.random.default_rng(1)
+    d = rng.normal(0.0, 2.0 * cfg["box"] / cfg["n_part"], (3, cfg["n_part"] ** 3))
+    t_pair = pair_time(big, d)
+    t_eval = ratio * t_pair
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return dict(value=round(1.0 / t_eval, 6), unit="grad evals/s", cores=min(cores, 16),
+                kind="oracle",
+                sample="oracle CIC paint + readout of the %d^3 particle set (%.1f s) x "
+                       "ratio %.1f of a full oracle loss+gradient to that pair measured at "
+                       "64^3 on the same configuration; estimated %.0f s per evaluation"
+                       % (cfg["n_part"], t_pair, ratio, t_eval),
+                seconds_per_eval=round(t_eval, 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path is single-GPU (multi-GPU sharding is "
+              "a design note, not built); got --gpus %d" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_26823_amd import _lib, inputs
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2604_26823_amd import build
+        build.build()
+    cfg = inputs.config(a.config)
+    R = inputs.response_field(cfg)
+    cfg["nbar"] = inputs.nbar_for(cfg, R)
+    rom_every = cfg["rom_every"]
+
+    log("bench: building FP32 context for %s" % WORKLOAD[a.config])
+    ctx, s, counts, s_start = setup(cfg, "f32")
+    log("bench: FP32 warmup %d + timed %d steps" % (a.warmup, a.steps))
+    r32 = timed_loop(ctx, s, a.steps, a.warmup, rom_every)
+    log("bench: FP32 %d evals in %.3f s" % (r32["evals"], r32["seconds"]))
+    log("bench: per-kernel timing pass (%d steps)" % a.profile_steps)
+    rows = kernel_table(ctx, s, r32["g"], r32["loss"], a.warmup + a.steps, a.profile_steps,
+                        rom_every)
+    roof, table = roofline(rows)
+    ws_gb = ctx.ws_bytes / 1e9
+    del ctx, s
+    r32.pop("g")
+    torch.cuda.empty_cache()
+
+    r64 = None
+    if not a.no_fp64:
+        log("bench: FP64 context")
+        ctx64, s64, _, _ = setup(cfg, "f64", counts, s_start)
+        r64 = timed_loop(ctx64, s64, a.steps, a.warmup, rom_every)
+        r64.pop("g")
+        log("bench: FP64 %d evals in %.3f s" % (r64["evals"], r64["seconds"]))
+        del ctx64, s64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("bench: CPU oracle sample")
+        cpu = cpu_baseline(cfg)
+
+    value = r32["evals"] / r32["seconds"]
+    out = {
+        "metric": "PM forward+adjoint grad evals/s at 256^3, FP32 vs FP64, % HBM peak",
+        "value": round(value, 3),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * r32["seconds"] / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD[a.config], "n_part": cfg["n_part"],
+                   "n_mesh": cfg["n_mesh"], "box": cfg["box"], "n_steps": cfg["n_steps"],
+                   "rom_every": rom_every, "parallelism": "single GPU"},
+        "evaluations": r32["evals"],
+        "rom_events": r32["roms"],
+        "final_loss": r32["loss"],
+        "fp64": None if r64 is None else {
+            "value": round(r64["evals"] / r64["seconds"], 3), "unit": "grad evals/s",
+            "evaluations": r64["evals"], "ms_per_step": round(1e3 * r64["seconds"] / a.steps, 3)},
+        "roofline": roof,
+        "kernels": table,
+        "workspace_gb": round(ws_gb, 2),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -673,6 +673,10 @@ class Engine final : public EngineBase {
   T* dbg_key_[2];
   uint32_t* dbg_bin_;
   long long dbg_n_[2] = {-1, -1};
+  // Host staging of the Fourier-space bin counts and starts; members so that
+  // asynchronous copies never outlive their source.
+  std::vector<uint32_t> bin_count_ = std::vector<uint32_t>(256, 0);
+  std::vector<uint32_t> bin_start_ = std::vector<uint32_t>(128, 0);
   const int32_t* counts_ = nullptr;
   const T* resp_ = nullptr;
   KernelTimer timer_;

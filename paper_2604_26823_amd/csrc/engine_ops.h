@@ -100,10 +100,11 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
   IC_LAUNCHED();
   rk::k_bin_count<<<G, kThreads, 0, st_>>>(keys_, binc_, Hp_);
   IC_LAUNCHED();
-  std::vector<uint32_t> counts(256);
+  std::vector<uint32_t>& counts = bin_count_;
   IC_HIP(hipMemcpyAsync(counts.data(), binc_, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
   IC_HIP(hipStreamSynchronize(st_));
-  std::vector<uint32_t> start(128, 0);
+  std::vector<uint32_t>& start = bin_start_;
+  std::fill(start.begin(), start.end(), 0u);
   long long n = 0;
   int used = 0;
   for (int b = 0; b < nbins; ++b) {

@@ -84,10 +84,11 @@ __global__ void k_lpt_assemble(T* __restrict__ d, T* __restrict__ p, T cd1, T cd
 }
 
 // Observation model and loss on the data grid.  delta = rho - 1 (one particle
-// per data cell on average); lambda = nbar R (1 + b delta); masked cells
-// (R >= r_min) add (N - lambda)^2 / (nbar R) to chi^2 and get the adjoint
-// seed b nbar R (lambda - N) / (nbar R).  Per-block FP64 partial sums of
-// chi^2, |s|^2 and the masked-cell count go to part[3 * block + k].
+// per data cell on average); lambda = nbar R (1 + b delta) when R is given;
+// with counts also given, masked cells (R >= r_min) add (N - lambda)^2 /
+// (nbar R) to chi^2 and get the adjoint seed b nbar R (lambda - N) / (nbar R).
+// Per-block FP64 partial sums of chi^2, |s|^2 and the masked-cell count go to
+// part[3 * block + k].
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_loss(
     const T* __restrict__ rho, const int* __restrict__ counts, const T* __restrict__ R,
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
       const T r = R[i];
       const T lam = nbar * r * (T(1) + bias * delta);
       if (lambda_out) lambda_out[i] = lam;
-      if (r >= r_min) {
+      if (counts && r >= r_min) {
         const T var = nbar * r;
         const double res = static_cast<double>(counts[i]) - static_cast<double>(lam);
         chi += res * res / static_cast<double>(var);

@@ -55,6 +55,7 @@ def config(c, **overrides):
     """A copy of configuration c with overrides applied."""
     cfg = dict(CONFIGS[c])
     cfg["id"] = c
+    cfg["seed"] = seeds(c)["key"]
     cfg.update(overrides)
     return cfg
 

@@ -45,7 +45,9 @@ def test_forward_density(prec, name):
     cfg, mdl, ctx, R, N, s0 = prepared(name, prec)
     out = ctx.forward(to_dev(s0, prec), delta=True, lam=True, loss=True)
     L_ref, st = mdl.loss(s0, N, R, return_state=True)
-    assert rel_l2(to_np(out["delta"]), st["delta_s"]) <= TOL_DENS[prec]
+    err = rel_l2(to_np(out["delta"]), st["delta_s"])
+    print("density rel L2 %.3e, loss rel %.3e" % (err, abs(out["loss"] - L_ref) / abs(L_ref)))
+    assert err <= TOL_DENS[prec]
     assert abs(out["loss"] - L_ref) <= TOL_DENS[prec] * abs(L_ref)
 
 
@@ -56,6 +58,8 @@ def test_loss_and_gradient(prec, name):
     cfg, mdl, ctx, R, N, s0 = prepared(name, prec)
     L, g, terms = ctx.loss_and_grad(to_dev(s0, prec))
     L_ref, g_ref, st = mdl.loss_and_grad(s0, N, R)
+    print("loss rel %.3e, gradient rel L2 %.3e" % (abs(L - L_ref) / abs(L_ref),
+                                                    rel_l2(to_np(g), g_ref)))
     assert abs(L - L_ref) <= TOL_DENS[prec] * abs(L_ref)
     assert abs(terms["chi2"] - st["chi2"]) <= TOL_DENS[prec] * abs(st["chi2"])
     assert rel_l2(to_np(g), g_ref) <= TOL_GRAD[prec]
