@@ -321,6 +321,7 @@ class Engine final : public EngineBase {
   pk::Rsd<T> rsd() const {
     pk::Rsd<T> r;
     r.mode = prob_.rsd_mode;
+    r.n = np_;
     r.c = static_cast<T>(co_.rsd_factor);
     r.box = static_cast<T>(prob_.box);
     r.dq = static_cast<T>(prob_.box / np_);

@@ -183,11 +183,32 @@ __global__ __launch_bounds__(256) void k_pm_step(const T* __restrict__ dcur, T* 
 template <typename T>
 struct Rsd {
   int mode;
+  int n;  // lattice side
   T c;
   T box;
   T dq;
   T obs[3];
 };
+
+// Periodic image in [0, box) of the position idx * dq + d along one axis.
+// Which image is taken is decided by comparing d with the exactly
+// representable distances to the box faces, -idx dq and (n - idx) dq, rather
+// than by rounding the sum first: the line of sight from a corner observer
+// jumps at the faces, and this keeps FP32 on the same side as the exact
+// position unless d itself is within its own rounding of a face.
+template <typename T>
+__device__ __forceinline__ T wrap_position(int idx, T d, const Rsd<T>& r) {
+  const T lo = -static_cast<T>(idx) * r.dq;
+  const T hi = static_cast<T>(r.n - idx) * r.dq;
+  if (d >= lo && d < hi) return static_cast<T>(idx) * r.dq + d;
+  if (d >= hi && d < hi + r.box) return static_cast<T>(idx - r.n) * r.dq + d;
+  if (d < lo && d >= lo - r.box) return static_cast<T>(idx + r.n) * r.dq + d;
+  const T x = static_cast<T>(idx) * r.dq + d;
+  T y = x - r.box * floor(x / r.box);
+  if (y < T(0)) y += r.box;
+  if (y >= r.box) y -= r.box;
+  return y;
+}
 
 template <typename T>
 __device__ __forceinline__ void los(const Rsd<T>& r, const int idx[3], const T dsp[3], T u[3],
@@ -195,8 +216,7 @@ __device__ __forceinline__ void los(const Rsd<T>& r, const int idx[3], const T d
   T rr = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T x = static_cast<T>(idx[a]) * r.dq + dsp[a];
-    const T y = x - r.box * floor(x / r.box);
+    const T y = wrap_position(idx[a], dsp[a], r);
     u[a] = y - r.obs[a];
     rr += u[a] * u[a];
   }
