@@ -187,9 +187,14 @@ int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
 
 /* One projected L-BFGS iteration (section 2.3.1): direction from the
  * two-loop recursion over the stored pairs (FP64 dot products), backtracking
- * line search along P(s + eps p) from eps_max with the Armijo test, history
- * update.  s, grad: device in/out (n_part^3); loss: host in/out; iteration
- * keys the reset draws.  Returns IC_ERR_LINESEARCH when no trial passes. */
+ * line search along the projection arc s' = P(s + eps p) from eps_max,
+ * halving, accepting when g.(s' - s) < 0, L(s') < L and
+ * L(s') <= L + c1 g.(s' - s);
+ * if that fails for a quasi-Newton direction, the history is reset and
+ * steepest descent is searched once more.  Then the (S, Y) pair update.
+ * s, grad: device in/out (n_part^3); loss: host in/out; iteration keys the
+ * reset draws.  Returns IC_ERR_LINESEARCH when no trial passes (s, grad and
+ * loss are then unchanged). */
 int ic_lbfgs_step(ic_ctx* ctx, void* s, void* grad, double* loss, int64_t iteration,
                   ic_lbfgs_info* info);
 

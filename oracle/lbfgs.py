@@ -6,12 +6,18 @@ s + eps p, P being the projection of ``oracle.projection``.  Appendix B sets
 the maximum step eps_max = 1 for the method.
 
 Readings where the paper is silent: backtracking from eps_max, halving, up to
-30 trials, Armijo test L(s') <= L(s) + c1 eps (g . p) with c1 = 1e-4 against
-the unprojected directional derivative; initial inverse Hessian gamma I with
-gamma = S.Y / Y.Y of the newest pair (1 with an empty history, natural since
-the prior's Hessian is the identity); a pair is stored only when
+30 trials, with the sufficient-decrease (Armijo) test taken along the
+projection arc, L(s') <= L(s) + c1 g.(s' - s) with c1 = 1e-4,
+g.(s' - s) < 0 and L(s') < L(s) (the last rejects steps the projection
+undoes, whose predicted decrease is rounding noise) (Bertsekas' rule for projected line searches: the projection
+rescales long steps, so the unprojected eps g.p would demand far more
+decrease than any projected step can give); initial inverse Hessian gamma I
+with gamma = S.Y / Y.Y of the newest pair (1 with an empty history, natural
+since the prior's Hessian is the identity); a pair is stored only when
 S.Y > 1e-10 |S| |Y|; the history holds m = 10 pairs; a non-descent direction
-resets the history and falls back to -g.  All dot products are FP64.
+resets the history and falls back to -g, and so does a quasi-Newton
+direction whose line search fails (trials then continue numbering from
+max_trials).  All dot products are FP64.
 """
 import numpy as np
 
@@ -54,12 +60,30 @@ class ProjectedLBFGS:
             r = r + (a - b) * S
         return -r
 
+    def _search(self, s, g, L, p, fun, iteration, first_trial):
+        """Backtracking along the projection arc; returns (accepted, trial,
+        eps, s', g', L', resets)."""
+        eps = self.eps_max
+        for k in range(self.max_trials):
+            trial = first_trial + k
+            s_t, resets = project(s + eps * p, self.s_th, self.seed, iteration, trial)
+            L_t, g_t = fun(s_t)
+            g_t = np.asarray(g_t, dtype=np.float64).reshape(-1)
+            s_t = s_t.reshape(-1)
+            self._evals += 1
+            decrease = float(np.dot(g, s_t - s))
+            if decrease < 0 and L_t < L and L_t <= L + self.c1 * decrease:
+                return True, trial, eps, s_t, g_t, L_t, resets
+            eps *= 0.5
+        return False, trial, eps, None, None, None, resets
+
     def step(self, s, g, L, fun, iteration):
         """One projected L-BFGS iteration.
 
         fun(s) -> (L, g).  Returns (s', g', L', info)."""
         s = np.asarray(s, dtype=np.float64).reshape(-1)
         g = np.asarray(g, dtype=np.float64).reshape(-1)
+        self._evals = 0
         p = self.direction(g)
         gp = float(np.dot(g, p))
         restarted = False
@@ -68,15 +92,16 @@ class ProjectedLBFGS:
             p = -g
             gp = float(np.dot(g, p))
             restarted = True
-        eps = self.eps_max
-        for trial in range(self.max_trials):
-            s_t, resets = project(s + eps * p, self.s_th, self.seed, iteration, trial)
-            L_t, g_t = fun(s_t)
-            g_t = np.asarray(g_t, dtype=np.float64).reshape(-1)
-            if L_t <= L + self.c1 * eps * gp:
-                break
-            eps *= 0.5
-        else:
+        accepted, trial, eps, s_t, g_t, L_t, resets = self._search(s, g, L, p, fun,
+                                                                    iteration, 0)
+        if not accepted and self.S:
+            self.reset()
+            p = -g
+            gp = float(np.dot(g, p))
+            restarted = True
+            accepted, trial, eps, s_t, g_t, L_t, resets = self._search(
+                s, g, L, p, fun, iteration, self.max_trials)
+        if not accepted:
             raise LineSearchError("no acceptable step in %d trials" % self.max_trials)
         S = s_t - s
         Y = g_t - g
@@ -88,6 +113,7 @@ class ProjectedLBFGS:
             if len(self.S) > self.m:
                 self.S.pop(0)
                 self.Y.pop(0)
-        info = dict(eps=eps, trials=trial + 1, resets=resets, stored=bool(stored),
+        info = dict(eps=eps, trials=trial + 1, evaluations=self._evals, resets=resets,
+                    stored=bool(stored),
                     restarted=restarted, history=len(self.S), gp=gp)
         return s_t, g_t, L_t, info

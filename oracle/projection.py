@@ -23,7 +23,8 @@ def project(s, s_th, seed, event, trial):
     mean = np.sum(flat) / n
     dev = flat - mean
     std = np.sqrt(np.sum(dev * dev) / n)
-    z = dev / std
+    with np.errstate(invalid="ignore", divide="ignore"):
+        z = dev / std  # a constant input has no z-score: NaN, rejected by the line search
     bad = np.nonzero(np.abs(z) > s_th)[0]
     out = z.copy()
     if bad.size:

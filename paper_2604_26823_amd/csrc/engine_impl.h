@@ -359,6 +359,15 @@ class Engine final : public EngineBase {
     return r;
   }
 
+  double dot_diff(const T* g, const T* a, const T* b) {
+    const unsigned gr = grid_for(P_, fk::kRedThreads, kRedBlocks);
+    fk::k_dot_diff<T><<<gr, fk::kRedThreads, 0, st_>>>(g, a, b, part_, P_);
+    IC_LAUNCHED();
+    double r = 0;
+    reduce_parts(gr, 1, &r);
+    return r;
+  }
+
   long long count_nonfinite(const T* x, long long n) {
     const unsigned g = grid_for(n, fk::kRedThreads, kRedBlocks);
     fk::k_count_nonfinite<T><<<g, fk::kRedThreads, 0, st_>>>(x, part_, n);

@@ -173,22 +173,39 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
     gp = dot(g, dir_, P_);
     inf.restarted = 1;
   }
-  double eps = prob_.eps_max;
+  // Backtracking along the projection arc: accept s' = P(s + eps p) when
+  // g.(s' - s) < 0, L(s') < L and L(s') <= L + c1 g.(s' - s).  A quasi-Newton direction
+  // whose search fails is replaced once by steepest descent (history reset),
+  // with trial numbers continuing after max_trials.
+  double eps = 0;
   bool accepted = false;
   ic_loss_terms t{};
-  int trial = 0;
-  for (; trial < prob_.max_trials; ++trial) {
-    axpy(s, dir_, eps, strial_, P_);
-    inf.resets = project(strial_, strial_, (uint64_t)trial, (uint64_t)it);
-    eval(strial_, gtrial_, &t);
-    inf.evaluations++;
-    if (t.loss <= L + prob_.armijo_c1 * eps * gp) {
-      accepted = true;
-      break;
+  int used = 0;
+  for (int attempt = 0; attempt < 2 && !accepted; ++attempt) {
+    if (attempt == 1) {
+      if (hist_.empty()) break;
+      lbfgs_reset();
+      axpy(g, g, -2.0, dir_, P_);
+      gp = dot(g, dir_, P_);
+      inf.restarted = 1;
     }
-    eps *= 0.5;
+    eps = prob_.eps_max;
+    for (int k = 0; k < prob_.max_trials; ++k) {
+      const int trial = attempt * prob_.max_trials + k;
+      axpy(s, dir_, eps, strial_, P_);
+      inf.resets = project(strial_, strial_, (uint64_t)trial, (uint64_t)it);
+      eval(strial_, gtrial_, &t);
+      inf.evaluations++;
+      used = k + 1;
+      const double dec = dot_diff(g, strial_, s);
+      if (dec < 0 && t.loss < L && t.loss <= L + prob_.armijo_c1 * dec) {
+        accepted = true;
+        break;
+      }
+      eps *= 0.5;
+    }
   }
-  inf.trials = accepted ? trial + 1 : trial;
+  inf.trials = used;
   inf.gp = gp;
   if (!accepted) {
     if (info) *info = inf;

@@ -160,6 +160,22 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const T* __restrict__ a,
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Partial sums of g . (a - b) with the difference taken in FP64.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_dot_diff(const T* __restrict__ g,
+                                                          const T* __restrict__ a,
+                                                          const T* __restrict__ b,
+                                                          double* __restrict__ part,
+                                                          long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    acc += static_cast<double>(g[i]) * (static_cast<double>(a[i]) - static_cast<double>(b[i]));
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 // Partial sums of (x - mean)^2, mean = sum[0] / n read from device memory.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_centered_sq(const T* __restrict__ a,

@@ -204,7 +204,8 @@ def test_two_loop_equals_explicit_bfgs_matrix():
 
 def test_projected_lbfgs_monotone_on_quadratic():
     """On a convex quadratic whose minimiser is unaffected by the projection
-    scale, every accepted step satisfies Armijo and lowers the loss."""
+    scale, every accepted step satisfies the sufficient-decrease test along
+    the projection arc and lowers the loss."""
     rng = np.random.default_rng(26)
     d = 4096
     target = rng.standard_normal(d)
@@ -216,7 +217,27 @@ def test_projected_lbfgs_monotone_on_quadratic():
     L, g = fun(s)
     for k in range(15):
         s2, g2, L2, info = opt.step(s, g, L, fun, k)
-        assert L2 <= L + 1e-4 * info["eps"] * info["gp"]
+        dec = float(np.dot(g, s2 - s))
+        assert dec < 0 and L2 <= L + 1e-4 * dec      # Armijo along the projection arc
         assert L2 < L
         s, g, L = s2, g2, L2
     assert L < 1e-2 * fun(projection.project(rng.standard_normal(d), 10, 3, 0, 0)[0])[0]
+
+
+def test_line_search_restarts_with_steepest_descent():
+    """A quasi-Newton direction along s itself is undone by the projection
+    (P(s + eps c s) = s), so its line search cannot decrease the loss; the
+    step then resets the history and searches along -g."""
+    d = 1000
+    rng = np.random.default_rng(27)
+    s, _ = projection.project(rng.standard_normal(d), 10.0, 1, 0, 0)
+    target, _ = projection.project(rng.standard_normal(d), 10.0, 1, 0, 1)
+    fun = lambda x: (0.5 * np.sum((x - target) ** 2), x - target)
+    opt = lbfgs.ProjectedLBFGS(seed=1, max_trials=5)
+    opt.S.append(np.ones(d))
+    opt.Y.append(np.ones(d))
+    L, g = fun(s)
+    opt.direction = lambda gg: -np.sign(gg @ s) * s
+    s2, g2, L2, info = opt.step(s, g, L, fun, 0)
+    assert info["restarted"] and L2 < L
+    assert info["evaluations"] == info["trials"]  # 5 failed trials, then the -g search
