@@ -3,7 +3,7 @@
 One step is one projected L-BFGS iteration of the method (projection of
 s + eps p, loss + gradient evaluations of the line search, two-loop
 recursion with FP64 dot products, history update), with the rank-order
-matching event (projection + real-space + Fourier-space matching, history
+matching event (real-space + Fourier-space matching + projection, history
 reset, re-evaluation) every ``rom_every`` iterations, on the 256^3 survey-
 shaped synthetic workload (c3).  The metric is gradient evaluations per
 second: all loss + gradient evaluations made in the K timed steps divided by

@@ -177,11 +177,13 @@ int ic_loss_and_grad(ic_ctx* ctx, const void* s, void* grad, double* loss,
  * all device buffers of n_part^3. */
 int ic_vjp(ic_ctx* ctx, const void* s, const void* delta_bar, void* s_bar);
 
-/* In-place projection and rank-order matching of the white noise s
- * (sections 2.3.1-2.3.2), in the order projection, real-space matching on
- * M = 1 cells, Fourier-space matching of |z| per k bin; flags selects the
- * parts.  event keys the random draws (reset draws also use trial).
- * info is optional.  A rank-order pass fails with IC_ERR_NONFINITE on NaN. */
+/* In-place rank-order matching and projection of the white noise s
+ * (sections 2.3.1-2.3.2), in the order real-space matching on M = 1 cells,
+ * Fourier-space matching of |z| per k bin, projection P (z-score and reset
+ * of |s| > s_th, repeated until a pass resets nothing, so the result has
+ * mean 0, std 1 and no extremes); flags selects the parts.  event keys the
+ * random draws (reset draws also use trial).  info is optional.  A
+ * rank-order pass fails with IC_ERR_NONFINITE on NaN. */
 int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
                          int32_t trial, ic_rom_info* info);
 

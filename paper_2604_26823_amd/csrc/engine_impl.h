@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -176,7 +177,6 @@ class Engine final : public EngineBase {
     if (!sv) throw ApiError(IC_ERR_INVALID_ARG, "s is null");
     T* s = static_cast<T*>(sv);
     ic_rom_info inf{};
-    if (flags & IC_PROJECT) inf.resets = project(s, s, (uint64_t)trial, event);
     if (flags & (IC_ROM_REAL | IC_ROM_FOURIER)) {
       if (count_nonfinite(s, P_) > 0) throw ApiError(IC_ERR_NONFINITE, "non-finite input to matching");
     }
@@ -185,6 +185,7 @@ class Engine final : public EngineBase {
       inf.n_real = rom_real(s, event);
     }
     if (flags & IC_ROM_FOURIER) inf.n_fourier = rom_fourier(s, event, &inf.bins_used);
+    if (flags & IC_PROJECT) inf.resets = project(s, s, (uint64_t)trial, event);
     if (info) *info = inf;
   }
 
@@ -631,26 +632,39 @@ class Engine final : public EngineBase {
   }
 
   // ------------------------------------------------------------ projection
+  // P(x): z-score, reset |z| > s_th to the pass's draws, repeated until a pass
+  // resets nothing (the output then has mean 0, std 1 and no extremes, and P
+  // is idempotent on it); after kMaxProjectPasses passes with resets, a last
+  // z-score without resets keeps the moments exact.  Returns the reset count.
+  static constexpr int kMaxProjectPasses = 32;
+
   int project(const T* x, T* out, uint64_t trial, uint64_t event) {
     const unsigned g = grid_for(P_, fk::kRedThreads, kRedBlocks);
-    fk::k_dot<T><<<g, fk::kRedThreads, 0, st_>>>(x, nullptr, part_, P_);
-    IC_LAUNCHED();
-    fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, 1, scal_);
-    IC_LAUNCHED();
-    fk::k_centered_sq<T><<<g, fk::kRedThreads, 0, st_>>>(x, scal_, part_, P_);
-    IC_LAUNCHED();
-    fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, 1, scal_ + 1);
-    IC_LAUNCHED();
-    fk::k_project<T><<<g, fk::kRedThreads, 0, st_>>>(x, scal_, scal_ + 1,
-                                                     static_cast<T>(prob_.s_th), trial, event,
-                                                     prob_.seed, out, part_, P_);
-    IC_LAUNCHED();
-    fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, 1, scal_ + 2);
-    IC_LAUNCHED();
-    double r = 0;
-    IC_HIP(hipMemcpyAsync(&r, scal_ + 2, sizeof(double), hipMemcpyDeviceToHost, st_));
-    IC_HIP(hipStreamSynchronize(st_));
-    return (int)r;
+    auto sc = timer_.scope("project_pass", 4.0 * P_ * sizeT());
+    int total = 0;
+    const T* src = x;
+    for (int pass = 0; pass <= kMaxProjectPasses; ++pass) {
+      const bool last = pass == kMaxProjectPasses;
+      fk::k_dot<T><<<g, fk::kRedThreads, 0, st_>>>(src, nullptr, part_, P_);
+      IC_LAUNCHED();
+      fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, 1, scal_);
+      IC_LAUNCHED();
+      fk::k_centered_sq<T><<<g, fk::kRedThreads, 0, st_>>>(src, scal_, part_, P_);
+      IC_LAUNCHED();
+      fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, 1, scal_ + 1);
+      IC_LAUNCHED();
+      const T th = last ? std::numeric_limits<T>::infinity() : static_cast<T>(prob_.s_th);
+      fk::k_project<T><<<g, fk::kRedThreads, 0, st_>>>(src, scal_, scal_ + 1, th,
+                                                       trial + 1024ull * pass, event,
+                                                       prob_.seed, out, part_, P_);
+      IC_LAUNCHED();
+      double r = 0;
+      reduce_parts(g, 1, &r);
+      total += (int)r;
+      src = out;
+      if (r == 0) break;
+    }
+    return total;
   }
 
   // ------------------------------------------------------------------ ROM

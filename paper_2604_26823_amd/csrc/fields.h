@@ -267,14 +267,15 @@ __global__ void k_philox(int kind, uint64_t sub, uint64_t stream, uint64_t event
     out[i] = static_cast<T>(philox_draw(kind, (uint64_t)i, sub, stream, event, seed));
 }
 
-// Projection: out = (x - mean) / std with mean = sums[0]/n and
-// std = sqrt(sums[1]/n); |out| > s_th is replaced by the reset draw of that
-// element.  The reset count goes to part[block].
+// One projection pass: out = (x - mean) / std with mean = sum[0]/n and
+// std = sqrt(sq[0]/n); |out| > s_th is replaced by the reset draw of that
+// element (counter sub word = sub).  The reset count goes to part[block].
+// x may equal out.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_project(
-    const T* __restrict__ x, const double* __restrict__ sum, const double* __restrict__ sq,
-    T s_th, uint64_t trial, uint64_t event, uint64_t seed, T* __restrict__ out,
-    double* __restrict__ part, long long n) {
+    const T* x, const double* __restrict__ sum, const double* __restrict__ sq, T s_th,
+    uint64_t sub, uint64_t event, uint64_t seed, T* out, double* __restrict__ part,
+    long long n) {
   __shared__ double sh[kRedThreads / 64];
   const double mean = sum[0] / static_cast<double>(n);
   const double sd = sqrt(sq[0] / static_cast<double>(n));
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kRedThreads) void k_project(
        i += (long long)gridDim.x * blockDim.x) {
     T z = static_cast<T>((static_cast<double>(x[i]) - mean) / sd);
     if (fabs(z) > s_th) {
-      z = static_cast<T>(philox_draw(0, (uint64_t)i, trial, 1, event, seed));
+      z = static_cast<T>(philox_draw(0, (uint64_t)i, sub, 1, event, seed));
       resets += 1.0;
     }
     out[i] = z;

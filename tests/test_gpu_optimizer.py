@@ -112,9 +112,9 @@ def test_lbfgs_trajectory_matches_oracle(prec):
     for it in range(iters):
         s_ref, g_ref, L_ref, _ = opt.step(s_ref, g_ref, L_ref, fun, it)
         if (it + 1) % every == 0:
-            x, _ = projection.project(s_ref, 10.0, seed, it + 1, 0)
-            x, _ = rom.rom_real(x.reshape(n, n, n), R, cfg["r_min"], seed, it + 1)
+            x, _ = rom.rom_real(s_ref.reshape(n, n, n), R, cfg["r_min"], seed, it + 1)
             x, _ = rom.rom_fourier(x, cfg["box"], seed, it + 1)
+            x, _ = projection.project(x, 10.0, seed, it + 1, 0)
             s_ref = x.reshape(-1)
             opt.reset()
             L_ref, g_ref = fun(s_ref)

@@ -52,15 +52,31 @@ def test_projection_resets_planted_values():
     rng = np.random.default_rng(21)
     s = rng.standard_normal(4096)
     planted = [5, 77, 1000]
-    s[planted] = [400.0, -350.0, 500.0]
+    s[planted] = [15.0, -12.0, 20.0]
     out, nres = projection.project(s, 10.0, 9, 3, 2)
     assert nres == 3
-    ref = philox.normal(np.array(planted, dtype=np.uint64), 2, philox.STREAM_RESET, 3, 9)
-    assert np.array_equal(out[planted], ref)
-    keep = np.setdiff1d(np.arange(4096), planted)
+    # first pass: z-score, reset the three planted values with the pass-0 draws
     mu = s.mean()
     sd = np.sqrt(np.mean((s - mu) ** 2))
-    assert np.allclose(out[keep], (s[keep] - mu) / sd, rtol=0, atol=1e-15)
+    z = (s - mu) / sd
+    z[planted] = philox.normal(np.array(planted, dtype=np.uint64), 2, philox.STREAM_RESET, 3, 9)
+    # second pass resets nothing: the output is z re-standardised
+    mu2 = z.mean()
+    sd2 = np.sqrt(np.mean((z - mu2) ** 2))
+    assert np.allclose(out, (z - mu2) / sd2, rtol=0, atol=1e-14)
+    assert abs(out.mean()) <= 1e-15 and abs(out.std() - 1) <= 1e-14
+
+
+def test_projection_output_is_feasible_and_idempotent():
+    rng = np.random.default_rng(28)
+    s = rng.standard_normal(20000)
+    s[rng.integers(0, 20000, 300)] *= 400.0   # many extremes: several passes
+    out, nres = projection.project(s, 10.0, 4, 1, 0)
+    assert nres >= 300
+    assert abs(out.mean()) <= 1e-14 and abs(out.std() - 1) <= 1e-14
+    assert np.max(np.abs(out)) <= 10.0
+    again, n2 = projection.project(out, 10.0, 4, 2, 0)
+    assert n2 == 0 and np.max(np.abs(again - out)) <= 1e-14
 
 
 def test_projection_is_almost_identity_on_gaussian_samples():
