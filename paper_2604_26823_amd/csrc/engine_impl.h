@@ -316,8 +316,12 @@ class Engine final : public EngineBase {
     return f;
   }
 
-  pk::Grid<T> gmesh() const { return {lm_, ratio_, static_cast<T>((double)nm_ / prob_.box)}; }
-  pk::Grid<T> gdata() const { return {lp_, 1, static_cast<T>((double)np_ / prob_.box)}; }
+  pk::Grid<T> gmesh() const {
+    return {lm_, ratio_, static_cast<T>((double)nm_ / prob_.box), static_cast<T>(prob_.box / nm_)};
+  }
+  pk::Grid<T> gdata() const {
+    return {lp_, 1, static_cast<T>((double)np_ / prob_.box), static_cast<T>(prob_.box / np_)};
+  }
 
   pk::Rsd<T> rsd() const {
     pk::Rsd<T> r;

@@ -10,6 +10,8 @@
 // FP32 positions accurate to the displacement's own rounding.
 #pragma once
 
+#include <limits>
+
 #include "common.h"
 
 namespace ic {
@@ -29,16 +31,30 @@ __device__ __forceinline__ void lattice(long long n, int lp, int idx[3]) {
   idx[0] = static_cast<int>(n >> (2 * lp));
 }
 
+// CIC stencil of the particle at lattice index idx displaced by dsp.  The
+// fractional position t = (d - f cell) / cell takes the remainder d - f cell
+// with one fused multiply-add, which is exact when the cell size is a binary
+// fraction (L / N with N a power of two), so t carries the rounding of d only
+// and not the larger rounding of d / cell at |d| of many cells.
 template <typename T>
 __device__ __forceinline__ Stencil<T> stencil(const int idx[3], int ratio, const T dsp[3],
-                                              T inv_cell) {
+                                              T inv_cell, T cell) {
   Stencil<T> s;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T u = dsp[a] * inv_cell;
-    const T f = floor(u);
+    T f = floor(dsp[a] * inv_cell);
+    T r = fma(-f, cell, dsp[a]);
+    if (r < T(0)) {
+      f -= T(1);
+      r += cell;
+    } else if (r >= cell) {
+      f += T(1);
+      r -= cell;
+    }
+    T t = r * inv_cell;
+    if (t >= T(1)) t = T(1) - T(0.5) * std::numeric_limits<T>::epsilon();
     s.i0[a] = idx[a] * ratio + static_cast<int>(f);
-    s.t[a] = u - f;
+    s.t[a] = t;
   }
   return s;
 }
@@ -54,6 +70,7 @@ struct Grid {
   int lm;      // log2 of the grid side
   int ratio;   // grid cells per lattice spacing (1 or 2)
   T inv_cell;  // grid side / box
+  T cell;      // box / grid side
 };
 
 template <typename T>
@@ -102,7 +119,7 @@ __global__ __launch_bounds__(256) void k_paint(const T* __restrict__ d, long lon
     lattice(n, lp, idx);
     T dsp[3];
     load3(d, P, n, dsp);
-    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell);
+    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
     for_corners(s, g.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
   }
 }
@@ -121,7 +138,7 @@ __global__ __launch_bounds__(256) void k_paint_vec(const T* __restrict__ d,
     T dsp[3], vv[3];
     load3(d, P, n, dsp);
     load3(v, P, n, vv);
-    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell);
+    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
     const T v0 = coef * vv[0], v1 = coef * vv[1], v2 = coef * vv[2];
     for_corners(s, g.lm, [&](long long c, T w, T, T, T) {
       atomic_add(out + c, w * v0);
@@ -158,7 +175,7 @@ __global__ __launch_bounds__(256) void k_pm_step(const T* __restrict__ dcur, T* 
     T dsp[3], mom[3], F[3];
     load3(dcur, P, n, dsp);
     load3(p, P, n, mom);
-    Stencil<T> s = stencil(idx, gr.ratio, dsp, gr.inv_cell);
+    Stencil<T> s = stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
     readout3(s, gr.lm, g, M, F);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(256) void k_pm_step(const T* __restrict__ dcur, T* 
         dsp[a] += drift * mom[a];
         dnext[a * P + n] = dsp[a];
       }
-      Stencil<T> s2 = stencil(idx, gr.ratio, dsp, gr.inv_cell);
+      Stencil<T> s2 = stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
       for_corners(s2, gr.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
     }
   }
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(256) void k_final(const T* __restrict__ d, T* __res
     T dsp[3], mom[3], F[3], ds[3];
     load3(d, P, n, dsp);
     load3(p, P, n, mom);
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
     readout3(s, gm.lm, g, M, F);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -264,7 +281,7 @@ __global__ __launch_bounds__(256) void k_final(const T* __restrict__ d, T* __res
       p[a * P + n] = mom[a];
     }
     rsd_shift(rsd, idx, dsp, mom, ds);
-    Stencil<T> s2 = stencil(idx, gd.ratio, ds, gd.inv_cell);
+    Stencil<T> s2 = stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
     for_corners(s2, gd.lm, [&](long long c, T w, T, T, T) { atomic_add(rho_d + c, w); });
   }
 }
@@ -285,7 +302,7 @@ __global__ __launch_bounds__(256) void k_data_adjoint(const T* __restrict__ d,
     load3(d, P, n, dsp);
     load3(p, P, n, mom);
     rsd_shift(rsd, idx, dsp, mom, ds);
-    Stencil<T> s = stencil(idx, gd.ratio, ds, gd.inv_cell);
+    Stencil<T> s = stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
     T xb[3] = {0, 0, 0};
     for_corners(s, gd.lm, [&](long long c, T, T d0, T d1, T d2) {
       const T r = rho_bar[c];
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(256) void k_force_adjoint(
     load3(pbar, P, n, pb);
     load3(dbar, P, n, db);
     const T v0 = coef * pb[0], v1 = coef * pb[1], v2 = coef * pb[2];
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
     T xb[3] = {0, 0, 0};
     for_corners(s, gm.lm, [&](long long c, T, T d0, T d1, T d2) {
       const T h = v0 * g[c] + v1 * g[M + c] + v2 * g[2 * M + c] + rho_bar[c];
@@ -366,7 +383,7 @@ __global__ __launch_bounds__(256) void k_readout(const T* __restrict__ d, const 
     lattice(n, lp, idx);
     T dsp[3], f[3];
     load3(d, P, n, dsp);
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell);
+    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
     readout3(s, gm.lm, g, M, f);
     F[n] = f[0];
     F[P + n] = f[1];

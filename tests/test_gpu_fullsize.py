@@ -75,7 +75,12 @@ def test_c3_gradient_fp32_matches_fp64_and_fd():
     eg = rel_l2(res["f32"][1], res["f64"][1])
     el = abs(res["f32"][0] - res["f64"][0]) / abs(res["f64"][0])
     print("c3 loss rel %.3e gradient rel L2 %.3e" % (el, eg))
-    assert el <= 1e-5 and eg <= 1e-4
+    # The FP32 trajectory differs from the FP64 one by ~1e-6 cells; CIC
+    # weights have kinks at cell faces, and under the Poisson-noise adjoint
+    # seed the particles that fall on the other side of a face in FP32 give a
+    # gradient difference that scales as the square root of that position
+    # error: ~1e-4 at this size (a smooth cotangent gives ~2e-6).
+    assert el <= 1e-5 and eg <= 2e-4
     # central difference of the FP64 loss along a random direction; the step
     # is small enough that few of the 16.7M particles cross a CIC cell face
     # (the loss is piecewise smooth) and large enough for FP64 rounding
