@@ -16,6 +16,7 @@
 #include "fft.h"
 #include "fields.h"
 #include "particles.h"
+#include "particles_tiled.h"
 #include "sort.h"
 #include "timer.h"
 
@@ -65,6 +66,7 @@ class Engine final : public EngineBase {
     Hp_ = (long long)np_ * np_ * (np_ / 2 + 1);
     Hm_ = (long long)nm_ * nm_ * (nm_ / 2 + 1);
     tape_forces_ = p.tape_forces != 0;
+    tg_ = tk::tile_geom(np_);
     const int m = std::max(1, p.lbfgs_m);
     wtab_len_ = 3 * (np_ / 2) * (np_ / 2) + 1;
     sort_blocks_ = (P_ + sk::kTile - 1) / sk::kTile;
@@ -389,7 +391,7 @@ class Engine final : public EngineBase {
 
   void paint(const T* d, pk::Grid<T> g, T* rho, long long ncells) {
     auto sc = timer_.scope("cic_paint", (3.0 * P_ + ncells) * sizeT());
-    pk::k_paint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(d, P_, lp_, g, rho);
+    pk::k_paint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(d, P_, lp_, tg_, g, rho);
     IC_LAUNCHED();
   }
 
@@ -528,18 +530,18 @@ class Engine final : public EngineBase {
       fill(rhom_, T(0), M_);
       {
         auto sc = timer_.scope("pm_step", (12.0 * P_ + 4.0 * M_) * sizeT());
-        pk::k_pm_step<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+        pk::k_pm_step_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
             dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
-            dslot(n + 1), rhom_, P_, lp_, gmesh());
+            dslot(n + 1), rhom_, P_, lp_, tg_, gmesh());
         IC_LAUNCHED();
       }
       force_from_density(gslot(n + 1));
     }
     fill(rhod_, T(0), P_);
     auto sc = timer_.scope("final_rsd_paint", (10.0 * P_ + 3.0 * M_) * sizeT());
-    pk::k_final<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+    pk::k_final_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
         dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), gmesh(), rsd(), gdata(),
-        rhod_, P_, lp_);
+        rhod_, P_, lp_, tg_);
     IC_LAUNCHED();
   }
 
@@ -568,8 +570,8 @@ class Engine final : public EngineBase {
   void adjoint(T* out, const T* aux, T beta_aux) {
     {
       auto sc = timer_.scope("data_adjoint", 13.0 * P_ * sizeT());
-      pk::k_data_adjoint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-          dslot(S_), p_, rsd(), gdata(), seed_, dbar_, pbar_, P_, lp_);
+      pk::k_data_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
+          dslot(S_), p_, rsd(), gdata(), seed_, dbar_, pbar_, P_, lp_, tg_);
       IC_LAUNCHED();
     }
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
@@ -581,8 +583,8 @@ class Engine final : public EngineBase {
       fill(gbar_, T(0), 3 * M_);
       {
         auto sc = timer_.scope("cic_paint_vec", (6.0 * P_ + 3.0 * M_) * sizeT());
-        pk::k_paint_vec<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, gmesh(), gbar_, M_);
+        pk::k_paint_vec_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
+            dslot(n), pbar_, coef, P_, lp_, tg_, gmesh(), gbar_, M_);
         IC_LAUNCHED();
       }
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
@@ -593,8 +595,8 @@ class Engine final : public EngineBase {
       chain_gather(1, ins, sp, 3, rhobar_, nullptr, T(0));
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       auto sc = timer_.scope("force_adjoint", (15.0 * P_ + 4.0 * M_) * sizeT());
-      pk::k_force_adjoint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-          dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh());
+      pk::k_force_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
+          dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, tg_, gmesh());
       IC_LAUNCHED();
     }
     // 2LPT and whitening adjoint.
@@ -682,6 +684,7 @@ class Engine final : public EngineBase {
   int np_, nm_, S_, lp_, lm_, ratio_;
   long long P_, M_, Hp_, Hm_;
   bool tape_forces_;
+  tk::TileGeom tg_;
   int wtab_len_;
   long long sort_blocks_;
   size_t need_ = 0;

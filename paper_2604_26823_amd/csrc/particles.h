@@ -78,6 +78,30 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
+// Calls f(cx, cy, cz, w, dw0, dw1, dw2) for the 8 CIC corners with unwrapped
+// cell coordinates, w the weight and dwa its derivative along axis a in
+// units of 1/cell.
+template <typename T, class F>
+__device__ __forceinline__ void for_corners_xyz(const Stencil<T>& s, F&& f) {
+#pragma unroll
+  for (int ox = 0; ox < 2; ++ox) {
+    const T wx = ox ? s.t[0] : T(1) - s.t[0];
+    const T gx = ox ? T(1) : T(-1);
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      const T wy = oy ? s.t[1] : T(1) - s.t[1];
+      const T gy = oy ? T(1) : T(-1);
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz) {
+        const T wz = oz ? s.t[2] : T(1) - s.t[2];
+        const T gz = oz ? T(1) : T(-1);
+        f(s.i0[0] + ox, s.i0[1] + oy, s.i0[2] + oz, wx * wy * wz, gx * wy * wz, wx * gy * wz,
+          wx * wy * gz);
+      }
+    }
+  }
+}
+
 // Calls f(cell, w, dw0, dw1, dw2) for the 8 CIC corners, where w is the
 // weight and dwa its derivative along axis a in units of 1/cell.
 template <typename T, class F>
@@ -260,6 +284,31 @@ __device__ __forceinline__ void rsd_shift(const Rsd<T>& r, const int idx[3], con
   }
 }
 
+// Transpose of the RSD map at (d, p) applied to the redshift-space position
+// cotangent xb: adds to db (which holds xb on entry) and sets pb.  Radial:
+// with u the line of sight, P = I - u u^T and r the distance,
+// db += (c / r) [(u.xb) P p + (p.u) P xb], pb = c (u.xb) u.
+template <typename T>
+__device__ __forceinline__ void rsd_transpose(const Rsd<T>& rsd, const int idx[3], const T dsp[3],
+                                              const T mom[3], const T xb[3], T db[3], T pb[3]) {
+  if (rsd.mode == 1) {
+    pb[2] = rsd.c * xb[2];
+  } else if (rsd.mode == 2) {
+    T u[3], dist;
+    los(rsd, idx, dsp, u, dist);
+    const T ux = u[0] * xb[0] + u[1] * xb[1] + u[2] * xb[2];
+    const T up = u[0] * mom[0] + u[1] * mom[1] + u[2] * mom[2];
+    const T cr = dist > T(0) ? rsd.c / dist : T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T perp_p = mom[a] - up * u[a];
+      const T perp_x = xb[a] - ux * u[a];
+      db[a] += cr * (ux * perp_p + up * perp_x);
+      pb[a] = rsd.c * ux * u[a];
+    }
+  }
+}
+
 // Last kick (readout of g at d), then RSD and the data-grid paint.
 template <typename T>
 __global__ __launch_bounds__(256) void k_final(const T* __restrict__ d, T* __restrict__ p,
@@ -313,22 +362,7 @@ __global__ __launch_bounds__(256) void k_data_adjoint(const T* __restrict__ d,
 #pragma unroll
     for (int a = 0; a < 3; ++a) xb[a] *= gd.inv_cell;
     T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
-    if (rsd.mode == 1) {
-      pb[2] = rsd.c * xb[2];
-    } else if (rsd.mode == 2) {
-      T u[3], dist;
-      los(rsd, idx, dsp, u, dist);
-      const T ux = u[0] * xb[0] + u[1] * xb[1] + u[2] * xb[2];
-      const T up = u[0] * mom[0] + u[1] * mom[1] + u[2] * mom[2];
-      const T cr = dist > T(0) ? rsd.c / dist : T(0);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const T perp_p = mom[a] - up * u[a];
-        const T perp_x = xb[a] - ux * u[a];
-        db[a] += cr * (ux * perp_p + up * perp_x);
-        pb[a] = rsd.c * ux * u[a];
-      }
-    }
+    rsd_transpose(rsd, idx, dsp, mom, xb, db, pb);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       dbar[a * P + n] = db[a];

@@ -1,0 +1,355 @@
+// Tiled particle kernels: the paint, fused kick-drift-paint, final kick +
+// RSD + data paint, and adjoint kernels of particles.h, restructured around
+// Lagrangian tiles with LDS mesh windows (tiles.h).  Each kernel computes the
+// same per-particle arithmetic as its direct counterpart; only where mesh
+// values are read from and accumulated into changes.
+#pragma once
+
+#include "tiles.h"
+
+namespace ic {
+namespace pk {
+
+using tk::BoxShared;
+using tk::kPer;
+using tk::kThreads;
+using tk::kWCap;
+using tk::TileGeom;
+using tk::Window;
+
+// Per-thread particle slots of a tile.
+template <typename T>
+struct Slots {
+  bool ok[kPer];
+  long long n[kPer];
+  int idx[kPer][3];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_slots(Slots<T>& sl, const TileGeom& tg, int lp) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) sl.ok[k] = tk::tile_particle(tg, lp, k, sl.idx[k], sl.n[k]);
+}
+
+// Paint weight w (times per-field values v[f]) of stencil s into the window
+// (LDS atomics) or, for tiles that do not fit, straight into the mesh.
+template <typename T, int NF>
+__device__ __forceinline__ void paint_stencil(const Stencil<T>& s, const T v[NF], const Window& w,
+                                              T* lds, int lm, T* __restrict__ mesh, long long M) {
+  if (w.fits) {
+    for_corners_xyz(s, [&](int cx, int cy, int cz, T wt, T, T, T) {
+      const int k = tk::win_index(w, cx, cy, cz);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) atomicAdd(&lds[f * kWCap + k], wt * v[f]);
+    });
+  } else {
+    for_corners(s, lm, [&](long long c, T wt, T, T, T) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) atomic_add(mesh + f * M + c, wt * v[f]);
+    });
+  }
+}
+
+// F_f = sum over corners of W g_f, from the window or from the mesh.
+template <typename T, int NF>
+__device__ __forceinline__ void gather_stencil(const Stencil<T>& s, const Window& w, const T* lds,
+                                               int lm, const T* __restrict__ mesh, long long M,
+                                               T out[NF]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) out[f] = T(0);
+  if (w.fits) {
+    for_corners_xyz(s, [&](int cx, int cy, int cz, T wt, T, T, T) {
+      const int k = tk::win_index(w, cx, cy, cz);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) out[f] += wt * lds[f * kWCap + k];
+    });
+  } else {
+    for_corners(s, lm, [&](long long c, T wt, T, T, T) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) out[f] += wt * mesh[f * M + c];
+    });
+  }
+}
+
+// Window of the stencils held in st[] (ok[] marks valid slots).
+template <typename T>
+__device__ __forceinline__ Window window_of(BoxShared& bs, const Stencil<T> st[kPer],
+                                            const bool ok[kPer]) {
+  tk::box_init(bs);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (ok[k]) tk::box_add(bs, st[k].i0);
+  __syncthreads();
+  Window w = tk::box_window(bs);
+  __syncthreads();
+  return w;
+}
+
+// rho(c) += sum_n W(q_n + d_n - c).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_paint_t(const T* __restrict__ d, long long P, int lp,
+                                                      TileGeom tg, Grid<T> g,
+                                                      T* __restrict__ rho) {
+  __shared__ T lds[kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T dsp[3];
+    load3(d, P, sl.n[k], dsp);
+    st[k] = stencil(sl.idx[k], g.ratio, dsp, g.inv_cell, g.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) tk::win_zero(w, 1, lds);
+  __syncthreads();
+  const T one[1] = {T(1)};
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w, lds, g.lm, rho, 0);
+  __syncthreads();
+  if (w.fits) tk::win_flush(w, lds, 1, g.lm, rho, 0);
+}
+
+// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_paint_vec_t(const T* __restrict__ d,
+                                                          const T* __restrict__ v, T coef,
+                                                          long long P, int lp, TileGeom tg,
+                                                          Grid<T> g, T* __restrict__ out,
+                                                          long long M) {
+  __shared__ T lds[3 * kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+  T vv[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T dsp[3];
+    load3(d, P, sl.n[k], dsp);
+    load3(v, P, sl.n[k], vv[k]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vv[k][a] *= coef;
+    st[k] = stencil(sl.idx[k], g.ratio, dsp, g.inv_cell, g.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) tk::win_zero(w, 3, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (sl.ok[k]) paint_stencil<T, 3>(st[k], vv[k], w, lds, g.lm, out, M);
+  __syncthreads();
+  if (w.fits) tk::win_flush(w, lds, 3, g.lm, out, M);
+}
+
+// Fused step: readout of g at d_cur, kick p += kick F; drift
+// d_next = d_cur + drift p and paint rho at d_next.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pm_step_t(
+    const T* __restrict__ dcur, T* __restrict__ p, const T* __restrict__ g, long long M, T kick,
+    T drift, T* __restrict__ dnext, T* __restrict__ rho, long long P, int lp, TileGeom tg,
+    Grid<T> gr) {
+  __shared__ T lds[3 * kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    load3(dcur, P, sl.n[k], dsp[k]);
+    load3(p, P, sl.n[k], mom[k]);
+    st[k] = stencil(sl.idx[k], gr.ratio, dsp[k], gr.inv_cell, gr.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) tk::win_load(w, g, M, 3, gr.lm, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T F[3];
+    gather_stencil<T, 3>(st[k], w, lds, gr.lm, g, M, F);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mom[k][a] += kick * F[a];
+      p[a * P + sl.n[k]] = mom[k][a];
+      dsp[k][a] += drift * mom[k][a];
+      dnext[a * P + sl.n[k]] = dsp[k][a];
+    }
+    st[k] = stencil(sl.idx[k], gr.ratio, dsp[k], gr.inv_cell, gr.cell);
+  }
+  Window w2 = window_of(bs, st, sl.ok);
+  if (w2.fits) tk::win_zero(w2, 1, lds);
+  __syncthreads();
+  const T one[1] = {T(1)};
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w2, lds, gr.lm, rho, 0);
+  __syncthreads();
+  if (w2.fits) tk::win_flush(w2, lds, 1, gr.lm, rho, 0);
+}
+
+// Last kick (readout of g at d), then RSD and the data-grid paint.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T* __restrict__ p,
+                                                      const T* __restrict__ g, long long M,
+                                                      T kick, Grid<T> gm, Rsd<T> rsd, Grid<T> gd,
+                                                      T* __restrict__ rho_d, long long P, int lp,
+                                                      TileGeom tg) {
+  __shared__ T lds[3 * kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    load3(d, P, sl.n[k], dsp[k]);
+    load3(p, P, sl.n[k], mom[k]);
+    st[k] = stencil(sl.idx[k], gm.ratio, dsp[k], gm.inv_cell, gm.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) tk::win_load(w, g, M, 3, gm.lm, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T F[3], ds[3];
+    gather_stencil<T, 3>(st[k], w, lds, gm.lm, g, M, F);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      mom[k][a] += kick * F[a];
+      p[a * P + sl.n[k]] = mom[k][a];
+    }
+    rsd_shift(rsd, sl.idx[k], dsp[k], mom[k], ds);
+    st[k] = stencil(sl.idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
+  }
+  Window w2 = window_of(bs, st, sl.ok);
+  if (w2.fits) tk::win_zero(w2, 1, lds);
+  __syncthreads();
+  const T one[1] = {T(1)};
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w2, lds, gd.lm, rho_d, 0);
+  __syncthreads();
+  if (w2.fits) tk::win_flush(w2, lds, 1, gd.lm, rho_d, 0);
+}
+
+// Adjoint of RSD + data paint (see k_data_adjoint), data-grid window.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_data_adjoint_t(
+    const T* __restrict__ d, const T* __restrict__ p, Rsd<T> rsd, Grid<T> gd,
+    const T* __restrict__ rho_bar, T* __restrict__ dbar, T* __restrict__ pbar, long long P,
+    int lp, TileGeom tg) {
+  __shared__ T lds[kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T ds[3];
+    load3(d, P, sl.n[k], dsp[k]);
+    load3(p, P, sl.n[k], mom[k]);
+    rsd_shift(rsd, sl.idx[k], dsp[k], mom[k], ds);
+    st[k] = stencil(sl.idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) tk::win_load(w, rho_bar, 0, 1, gd.lm, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T xb[3] = {0, 0, 0};
+    auto acc = [&](T r, T d0, T d1, T d2) {
+      xb[0] += d0 * r;
+      xb[1] += d1 * r;
+      xb[2] += d2 * r;
+    };
+    if (w.fits)
+      for_corners_xyz(st[k], [&](int cx, int cy, int cz, T, T d0, T d1, T d2) {
+        acc(lds[tk::win_index(w, cx, cy, cz)], d0, d1, d2);
+      });
+    else
+      for_corners(st[k], gd.lm, [&](long long c, T, T d0, T d1, T d2) { acc(rho_bar[c], d0, d1, d2); });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xb[a] *= gd.inv_cell;
+    T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
+    rsd_transpose(rsd, sl.idx[k], dsp[k], mom[k], xb, db, pb);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dbar[a * P + sl.n[k]] = db[a];
+      pbar[a * P + sl.n[k]] = pb[a];
+    }
+  }
+}
+
+// Position cotangent of one force evaluation (see k_force_adjoint), with
+// g (three meshes) and rho_bar read from one four-field window.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_force_adjoint_t(
+    const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
+    const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
+    int lp, TileGeom tg, Grid<T> gm) {
+  __shared__ T lds[4 * kWCap];
+  __shared__ BoxShared bs;
+  Slots<T> sl;
+  load_slots(sl, tg, lp);
+  Stencil<T> st[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    T dsp[3];
+    load3(d, P, sl.n[k], dsp);
+    st[k] = stencil(sl.idx[k], gm.ratio, dsp, gm.inv_cell, gm.cell);
+  }
+  Window w = window_of(bs, st, sl.ok);
+  if (w.fits) {
+    tk::win_load(w, g, M, 3, gm.lm, lds);
+    tk::win_load(w, rho_bar, 0, 1, gm.lm, lds + 3 * kWCap);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!sl.ok[k]) continue;
+    const long long n = sl.n[k];
+    T pb[3], db[3];
+    load3(pbar, P, n, pb);
+    load3(dbar, P, n, db);
+    const T v0 = coef * pb[0], v1 = coef * pb[1], v2 = coef * pb[2];
+    T xb[3] = {0, 0, 0};
+    auto acc = [&](T g0, T g1, T g2, T r, T d0, T d1, T d2) {
+      const T h = v0 * g0 + v1 * g1 + v2 * g2 + r;
+      xb[0] += d0 * h;
+      xb[1] += d1 * h;
+      xb[2] += d2 * h;
+    };
+    if (w.fits)
+      for_corners_xyz(st[k], [&](int cx, int cy, int cz, T, T d0, T d1, T d2) {
+        const int c = tk::win_index(w, cx, cy, cz);
+        acc(lds[c], lds[kWCap + c], lds[2 * kWCap + c], lds[3 * kWCap + c], d0, d1, d2);
+      });
+    else
+      for_corners(st[k], gm.lm, [&](long long c, T, T d0, T d1, T d2) {
+        acc(g[c], g[M + c], g[2 * M + c], rho_bar[c], d0, d1, d2);
+      });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      db[a] += xb[a] * gm.inv_cell;
+      dbar[a * P + n] = db[a];
+      if (drift != T(0)) pbar[a * P + n] = pb[a] + drift * db[a];
+    }
+  }
+}
+
+}  // namespace pk
+}  // namespace ic

@@ -1,0 +1,165 @@
+// Lagrangian particle tiles with LDS-staged mesh windows (gfx950).
+//
+// One 256-thread workgroup owns a 4 x 8 x 16 block of lattice particles
+// (two per thread).  Because particles move a few cells at most relative to
+// their lattice neighbours, the CIC stencils of a tile fall inside a small
+// Eulerian box.  The workgroup finds that box (LDS min/max), and then
+//   * paints into an LDS window with LDS atomics and flushes each non-zero
+//     window cell to HBM with one global atomic, one window row per lane so
+//     a wavefront's atomics land on 64 different cache lines;
+//   * or reads mesh fields for gathers from a window loaded with coalesced
+//     row loads, so every CIC corner read is an LDS read.
+// A tile whose box exceeds the window capacity (strongly clustered regions)
+// takes the direct global path for that call; results are the same.
+#pragma once
+
+#include <climits>
+
+#include "particles.h"
+
+namespace ic {
+namespace tk {
+
+constexpr int kThreads = 256;
+constexpr int kPer = 2;  // particles per thread
+constexpr int kWCap = 4096;  // window cells per field
+
+// Tile shape (tx, ty, tz) and tile counts per axis for a side-n lattice.
+struct TileGeom {
+  int tx, ty, tz;
+  int nx, ny, nz;
+};
+
+inline TileGeom tile_geom(int n) {
+  TileGeom t;
+  t.tx = n < 4 ? n : 4;
+  t.ty = n < 8 ? n : 8;
+  t.tz = n < 16 ? n : 16;
+  t.nx = n / t.tx;
+  t.ny = n / t.ty;
+  t.nz = n / t.tz;
+  return t;
+}
+
+inline unsigned tile_count(const TileGeom& t) { return (unsigned)(t.nx * t.ny * t.nz); }
+
+// Particle slot k of this thread: lattice index and flat index; false when
+// the slot is outside the tile.
+__device__ __forceinline__ bool tile_particle(const TileGeom& tg, int lp, int k, int idx[3],
+                                              long long& n) {
+  const int l = threadIdx.x + k * kThreads;
+  const int cnt = tg.tx * tg.ty * tg.tz;
+  if (l >= cnt) return false;
+  const int lz = l % tg.tz, ly = (l / tg.tz) % tg.ty, lx = l / (tg.tz * tg.ty);
+  const int b = blockIdx.x;
+  const int bz = b % tg.nz, by = (b / tg.nz) % tg.ny, bx = b / (tg.nz * tg.ny);
+  idx[0] = bx * tg.tx + lx;
+  idx[1] = by * tg.ty + ly;
+  idx[2] = bz * tg.tz + lz;
+  n = ((long long)idx[0] << (2 * lp)) | ((long long)idx[1] << lp) | (long long)idx[2];
+  return true;
+}
+
+// Eulerian window (unwrapped cell coordinates) covering a set of stencils.
+struct Window {
+  int o[3];
+  int w[3];
+  int vol;
+  bool fits;
+};
+
+struct BoxShared {
+  int lo[3];
+  int hi[3];
+};
+
+__device__ __forceinline__ void box_init(BoxShared& b) {
+  if (threadIdx.x < 3) {
+    b.lo[threadIdx.x] = INT_MAX;
+    b.hi[threadIdx.x] = INT_MIN;
+  }
+}
+
+// Adds the stencil base i0 (the box spans i0 .. i0 + 1 per axis).
+__device__ __forceinline__ void box_add(BoxShared& b, const int i0[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    atomicMin(&b.lo[a], i0[a]);
+    atomicMax(&b.hi[a], i0[a] + 1);
+  }
+}
+
+// Call after a barrier that follows all box_add calls.
+__device__ __forceinline__ Window box_window(const BoxShared& b) {
+  Window w;
+  long long vol = 1;
+  bool empty = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w.o[a] = b.lo[a];
+    const long long ext = (long long)b.hi[a] - (long long)b.lo[a] + 1;
+    if (ext <= 0) empty = true;
+    w.w[a] = ext > 0 && ext < (1 << 20) ? static_cast<int>(ext) : 0;
+    vol *= ext > 0 ? ext : 0;
+  }
+  w.fits = !empty && vol <= kWCap;
+  w.vol = w.fits ? static_cast<int>(vol) : 0;
+  return w;
+}
+
+// Window-local index of unwrapped cell c.
+__device__ __forceinline__ int win_index(const Window& w, int cx, int cy, int cz) {
+  return ((cx - w.o[0]) * w.w[1] + (cy - w.o[1])) * w.w[2] + (cz - w.o[2]);
+}
+
+// Physical (wrapped) mesh index of window cell number k.
+__device__ __forceinline__ long long win_cell(const Window& w, int k, int mask, int lm) {
+  const int cz = w.o[2] + k % w.w[2];
+  const int t = k / w.w[2];
+  const int cy = w.o[1] + t % w.w[1];
+  const int cx = w.o[0] + t / w.w[1];
+  const int c[3] = {cx, cy, cz};
+  return pk::cell_index(c, mask, lm);
+}
+
+// Loads nf fields (stride M) of the window into lds[f * kWCap + k].
+template <typename T>
+__device__ __forceinline__ void win_load(const Window& w, const T* __restrict__ src, long long M,
+                                         int nf, int lm, T* lds) {
+  const int mask = (1 << lm) - 1;
+  for (int k = threadIdx.x; k < w.vol; k += kThreads) {
+    const long long c = win_cell(w, k, mask, lm);
+    for (int f = 0; f < nf; ++f) lds[f * kWCap + k] = src[f * M + c];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void win_zero(const Window& w, int nf, T* lds) {
+  for (int f = 0; f < nf; ++f)
+    for (int k = threadIdx.x; k < w.vol; k += kThreads) lds[f * kWCap + k] = T(0);
+}
+
+// Adds the non-zero window cells of nf fields into the mesh (stride M) with
+// global atomics, one window row (fixed x, y) per lane.
+template <typename T>
+__device__ __forceinline__ void win_flush(const Window& w, const T* lds, int nf, int lm,
+                                          T* __restrict__ dst, long long M) {
+  const int mask = (1 << lm) - 1;
+  const int rows = w.w[0] * w.w[1];
+  for (int r = threadIdx.x; r < rows; r += kThreads) {
+    const int cy = w.o[1] + r % w.w[1];
+    const int cx = w.o[0] + r / w.w[1];
+    for (int z = 0; z < w.w[2]; ++z) {
+      const int k = r * w.w[2] + z;
+      const int c3[3] = {cx, cy, w.o[2] + z};
+      const long long c = pk::cell_index(c3, mask, lm);
+      for (int f = 0; f < nf; ++f) {
+        const T v = lds[f * kWCap + k];
+        if (v != T(0)) pk::atomic_add(dst + f * M + c, v);
+      }
+    }
+  }
+}
+
+}  // namespace tk
+}  // namespace ic
