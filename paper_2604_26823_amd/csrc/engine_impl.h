@@ -105,6 +105,7 @@ class Engine final : public EngineBase {
     vbuf_ = c.take<T>(P_);
     tbuf_ = c.take<T>(P_);
     binc_ = c.take<uint32_t>(256);
+    ovf_ = c.take<uint32_t>(kOvfSlots);
     dbg_idx_[0] = c.take<uint32_t>(P_);
     dbg_key_[0] = c.take<T>(P_);
     dbg_idx_[1] = c.take<uint32_t>(Hp_);
@@ -293,8 +294,20 @@ class Engine final : public EngineBase {
     IC_HIP(hipStreamSynchronize(st_));
   }
 
-  void timing(bool enable) override { timer_.enable(enable); }
-  std::string timing_report() override { return timer_.report(); }
+  void timing(bool enable) override {
+    if (enable) {
+      ek_fill_u32(ovf_, 0u, kOvfSlots);
+    }
+    timer_.enable(enable);
+  }
+  std::string timing_report() override {
+    std::string r = timer_.report();
+    uint32_t cnt[kOvfSlots];
+    IC_HIP(hipMemcpyAsync(cnt, ovf_, sizeof(cnt), hipMemcpyDeviceToHost, st_));
+    IC_HIP(hipStreamSynchronize(st_));
+    for (int k = 0; k < 6; ++k) r += std::string(kOvfNames[k]) + " " + std::to_string(cnt[k]) + " 0 0\n";
+    return r;
+  }
 
  private:
   // ------------------------------------------------------------- helpers
@@ -336,8 +349,16 @@ class Engine final : public EngineBase {
     return r;
   }
 
+  // Window-overflow counter of a tiled kernel (only while timing is on).
+  unsigned* ovf(int k) const { return timer_.enabled() ? ovf_ + k : nullptr; }
+
   T* dslot(int n) const { return dtape_ + (long long)n * 3 * P_; }
   T* gslot(int n) const { return tape_forces_ ? gtape_ + (long long)n * 3 * M_ : gtape_; }
+
+  void ek_fill_u32(uint32_t* x, uint32_t v, long long n) {
+    fk::k_fill<uint32_t><<<grid_for(n, kThreads), kThreads, 0, st_>>>(x, v, n);
+    IC_LAUNCHED();
+  }
 
   void fill(T* x, T v, long long n) {
     fk::k_fill<T><<<grid_for(n, kThreads), kThreads, 0, st_>>>(x, v, n);
@@ -391,7 +412,8 @@ class Engine final : public EngineBase {
 
   void paint(const T* d, pk::Grid<T> g, T* rho, long long ncells) {
     auto sc = timer_.scope("cic_paint", (3.0 * P_ + ncells) * sizeT());
-    pk::k_paint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(d, P_, lp_, tg_, g, rho);
+    pk::k_paint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(d, P_, lp_, tg_, g, rho,
+                                                                   ovf(0));
     IC_LAUNCHED();
   }
 
@@ -532,7 +554,7 @@ class Engine final : public EngineBase {
         auto sc = timer_.scope("pm_step", (12.0 * P_ + 4.0 * M_) * sizeT());
         pk::k_pm_step_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
             dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
-            dslot(n + 1), rhom_, P_, lp_, tg_, gmesh());
+            dslot(n + 1), rhom_, P_, lp_, tg_, gmesh(), ovf(1));
         IC_LAUNCHED();
       }
       force_from_density(gslot(n + 1));
@@ -541,7 +563,7 @@ class Engine final : public EngineBase {
     auto sc = timer_.scope("final_rsd_paint", (10.0 * P_ + 3.0 * M_) * sizeT());
     pk::k_final_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
         dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), gmesh(), rsd(), gdata(),
-        rhod_, P_, lp_, tg_);
+        rhod_, P_, lp_, tg_, ovf(2));
     IC_LAUNCHED();
   }
 
@@ -571,7 +593,7 @@ class Engine final : public EngineBase {
     {
       auto sc = timer_.scope("data_adjoint", 13.0 * P_ * sizeT());
       pk::k_data_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-          dslot(S_), p_, rsd(), gdata(), seed_, dbar_, pbar_, P_, lp_, tg_);
+          dslot(S_), p_, rsd(), gdata(), seed_, dbar_, pbar_, P_, lp_, tg_, ovf(3));
       IC_LAUNCHED();
     }
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
@@ -584,7 +606,7 @@ class Engine final : public EngineBase {
       {
         auto sc = timer_.scope("cic_paint_vec", (6.0 * P_ + 3.0 * M_) * sizeT());
         pk::k_paint_vec_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, tg_, gmesh(), gbar_, M_);
+            dslot(n), pbar_, coef, P_, lp_, tg_, gmesh(), gbar_, M_, ovf(4));
         IC_LAUNCHED();
       }
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
@@ -596,7 +618,7 @@ class Engine final : public EngineBase {
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       auto sc = timer_.scope("force_adjoint", (15.0 * P_ + 4.0 * M_) * sizeT());
       pk::k_force_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-          dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, tg_, gmesh());
+          dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, tg_, gmesh(), ovf(5));
       IC_LAUNCHED();
     }
     // 2LPT and whitening adjoint.
@@ -698,7 +720,12 @@ class Engine final : public EngineBase {
   double *part_, *scal_;
   T *hist_S_, *hist_Y_, *dir_, *strial_, *gtrial_;
   uint64_t *keys_, *keys2_;
-  uint32_t *vals_, *vals2_, *small_, *shist_, *binc_;
+  uint32_t *vals_, *vals2_, *small_, *shist_, *binc_, *ovf_;
+  static constexpr int kOvfSlots = 8;
+  static constexpr const char* kOvfNames[6] = {"tiles_direct_paint", "tiles_direct_pm_step",
+                                               "tiles_direct_final", "tiles_direct_data_adjoint",
+                                               "tiles_direct_paint_vec",
+                                               "tiles_direct_force_adjoint"};
   T *vbuf_, *tbuf_;
   uint32_t* dbg_idx_[2];
   T* dbg_key_[2];

@@ -76,10 +76,18 @@ template <typename T>
 __device__ __forceinline__ Window window_of(BoxShared& bs, const Stencil<T> st[kPer],
                                             const bool ok[kPer]) {
   tk::box_init(bs);
-  __syncthreads();
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if (ok[k]) tk::box_add(bs, st[k].i0);
+  for (int k = 0; k < kPer; ++k) {
+    if (!ok[k]) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(lo[a], st[k].i0[a]);
+      hi[a] = max(hi[a], st[k].i0[a] + 1);
+    }
+  }
+  __syncthreads();
+  tk::box_add_range(bs, lo, hi);
   __syncthreads();
   Window w = tk::box_window(bs);
   __syncthreads();
@@ -90,7 +98,7 @@ __device__ __forceinline__ Window window_of(BoxShared& bs, const Stencil<T> st[k
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_t(const T* __restrict__ d, long long P, int lp,
                                                       TileGeom tg, Grid<T> g,
-                                                      T* __restrict__ rho) {
+                                                      T* __restrict__ rho, unsigned* __restrict__ ovf) {
   __shared__ T lds[kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -104,6 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_t(const T* __restrict__ d, l
     st[k] = stencil(sl.idx[k], g.ratio, dsp, g.inv_cell, g.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) tk::win_zero(w, 1, lds);
   __syncthreads();
   const T one[1] = {T(1)};
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_t(const T* __restrict__ 
                                                           const T* __restrict__ v, T coef,
                                                           long long P, int lp, TileGeom tg,
                                                           Grid<T> g, T* __restrict__ out,
-                                                          long long M) {
+                                                          long long M, unsigned* __restrict__ ovf) {
   __shared__ T lds[3 * kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -138,6 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_t(const T* __restrict__ 
     st[k] = stencil(sl.idx[k], g.ratio, dsp, g.inv_cell, g.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) tk::win_zero(w, 3, lds);
   __syncthreads();
 #pragma unroll
@@ -153,7 +163,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pm_step_t(
     const T* __restrict__ dcur, T* __restrict__ p, const T* __restrict__ g, long long M, T kick,
     T drift, T* __restrict__ dnext, T* __restrict__ rho, long long P, int lp, TileGeom tg,
-    Grid<T> gr) {
+    Grid<T> gr, unsigned* __restrict__ ovf) {
   __shared__ T lds[3 * kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -168,6 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_pm_step_t(
     st[k] = stencil(sl.idx[k], gr.ratio, dsp[k], gr.inv_cell, gr.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) tk::win_load(w, g, M, 3, gr.lm, lds);
   __syncthreads();
 #pragma unroll
@@ -185,6 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_pm_step_t(
     st[k] = stencil(sl.idx[k], gr.ratio, dsp[k], gr.inv_cell, gr.cell);
   }
   Window w2 = window_of(bs, st, sl.ok);
+  tk::count_overflow(w2, ovf);
   if (w2.fits) tk::win_zero(w2, 1, lds);
   __syncthreads();
   const T one[1] = {T(1)};
@@ -201,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T
                                                       const T* __restrict__ g, long long M,
                                                       T kick, Grid<T> gm, Rsd<T> rsd, Grid<T> gd,
                                                       T* __restrict__ rho_d, long long P, int lp,
-                                                      TileGeom tg) {
+                                                      TileGeom tg, unsigned* __restrict__ ovf) {
   __shared__ T lds[3 * kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -216,6 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T
     st[k] = stencil(sl.idx[k], gm.ratio, dsp[k], gm.inv_cell, gm.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) tk::win_load(w, g, M, 3, gm.lm, lds);
   __syncthreads();
 #pragma unroll
@@ -232,6 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T
     st[k] = stencil(sl.idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
   }
   Window w2 = window_of(bs, st, sl.ok);
+  tk::count_overflow(w2, ovf);
   if (w2.fits) tk::win_zero(w2, 1, lds);
   __syncthreads();
   const T one[1] = {T(1)};
@@ -247,7 +261,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_data_adjoint_t(
     const T* __restrict__ d, const T* __restrict__ p, Rsd<T> rsd, Grid<T> gd,
     const T* __restrict__ rho_bar, T* __restrict__ dbar, T* __restrict__ pbar, long long P,
-    int lp, TileGeom tg) {
+    int lp, TileGeom tg, unsigned* __restrict__ ovf) {
   __shared__ T lds[kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -264,6 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_data_adjoint_t(
     st[k] = stencil(sl.idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) tk::win_load(w, rho_bar, 0, 1, gd.lm, lds);
   __syncthreads();
 #pragma unroll
@@ -299,7 +314,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_force_adjoint_t(
     const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
     const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
-    int lp, TileGeom tg, Grid<T> gm) {
+    int lp, TileGeom tg, Grid<T> gm, unsigned* __restrict__ ovf) {
   __shared__ T lds[4 * kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
@@ -313,6 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_t(
     st[k] = stencil(sl.idx[k], gm.ratio, dsp, gm.inv_cell, gm.cell);
   }
   Window w = window_of(bs, st, sl.ok);
+  tk::count_overflow(w, ovf);
   if (w.fits) {
     tk::win_load(w, g, M, 3, gm.lm, lds);
     tk::win_load(w, rho_bar, 0, 1, gm.lm, lds + 3 * kWCap);

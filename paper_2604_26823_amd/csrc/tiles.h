@@ -43,6 +43,17 @@ inline TileGeom tile_geom(int n) {
 
 inline unsigned tile_count(const TileGeom& t) { return (unsigned)(t.nx * t.ny * t.nz); }
 
+// Workgroups are dealt to the eight XCDs round-robin (block b runs on XCD
+// b mod 8).  Tile t = (b mod 8) * (count / 8) + b / 8 gives each XCD one
+// contiguous slab of tiles, so the halo cache lines that neighbouring tiles
+// share are read and updated in the same L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_tile(int b, int count) {
+  if (count % kXcds != 0) return b;
+  return (b % kXcds) * (count / kXcds) + b / kXcds;
+}
+
 // Particle slot k of this thread: lattice index and flat index; false when
 // the slot is outside the tile.
 __device__ __forceinline__ bool tile_particle(const TileGeom& tg, int lp, int k, int idx[3],
@@ -51,7 +62,7 @@ __device__ __forceinline__ bool tile_particle(const TileGeom& tg, int lp, int k,
   const int cnt = tg.tx * tg.ty * tg.tz;
   if (l >= cnt) return false;
   const int lz = l % tg.tz, ly = (l / tg.tz) % tg.ty, lx = l / (tg.tz * tg.ty);
-  const int b = blockIdx.x;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int bz = b % tg.nz, by = (b / tg.nz) % tg.ny, bx = b / (tg.nz * tg.ny);
   idx[0] = bx * tg.tx + lx;
   idx[1] = by * tg.ty + ly;
@@ -80,12 +91,24 @@ __device__ __forceinline__ void box_init(BoxShared& b) {
   }
 }
 
-// Adds the stencil base i0 (the box spans i0 .. i0 + 1 per axis).
-__device__ __forceinline__ void box_add(BoxShared& b, const int i0[3]) {
+// Adds this thread's range lo .. hi (per axis) to the box: reduced across
+// the wavefront with shuffles first, so each wave issues one LDS atomic per
+// bound instead of 64 contending ones.
+__device__ __forceinline__ void box_add_range(BoxShared& b, int lo[3], int hi[3]) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    atomicMin(&b.lo[a], i0[a]);
-    atomicMax(&b.hi[a], i0[a] + 1);
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&b.lo[a], lo[a]);
+      atomicMax(&b.hi[a], hi[a]);
+    }
   }
 }
 
@@ -122,14 +145,36 @@ __device__ __forceinline__ long long win_cell(const Window& w, int k, int mask, 
   return pk::cell_index(c, mask, lm);
 }
 
-// Loads nf fields (stride M) of the window into lds[f * kWCap + k].
+// Loads nf fields (stride M) of the window into lds[f * kWCap + k].  Each
+// thread issues the loads of kBatch cells before storing any of them, so the
+// loads of a batch are in flight together instead of one at a time.
+constexpr int kBatch = 8;
+
 template <typename T>
 __device__ __forceinline__ void win_load(const Window& w, const T* __restrict__ src, long long M,
                                          int nf, int lm, T* lds) {
   const int mask = (1 << lm) - 1;
-  for (int k = threadIdx.x; k < w.vol; k += kThreads) {
-    const long long c = win_cell(w, k, mask, lm);
-    for (int f = 0; f < nf; ++f) lds[f * kWCap + k] = src[f * M + c];
+  for (int base = 0; base < w.vol; base += kBatch * kThreads) {
+    T v[kBatch][4];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = base + j * kThreads + threadIdx.x;
+      if (k < w.vol) {
+        const long long c = win_cell(w, k, mask, lm);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          if (f < nf) v[j][f] = src[f * M + c];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = base + j * kThreads + threadIdx.x;
+      if (k < w.vol) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          if (f < nf) lds[f * kWCap + k] = v[j][f];
+      }
+    }
   }
 }
 
@@ -140,25 +185,41 @@ __device__ __forceinline__ void win_zero(const Window& w, int nf, T* lds) {
 }
 
 // Adds the non-zero window cells of nf fields into the mesh (stride M) with
-// global atomics, one window row (fixed x, y) per lane.
+// global atomics.  Consecutive lanes take consecutive window cells (rows run
+// along z), so a wavefront's atomics fall on a few cache lines: the memory
+// system applies all lanes that hit one line in a single operation, which is
+// what makes the flush cheap compared with one atomic stream per particle.
 template <typename T>
 __device__ __forceinline__ void win_flush(const Window& w, const T* lds, int nf, int lm,
                                           T* __restrict__ dst, long long M) {
   const int mask = (1 << lm) - 1;
-  const int rows = w.w[0] * w.w[1];
-  for (int r = threadIdx.x; r < rows; r += kThreads) {
-    const int cy = w.o[1] + r % w.w[1];
-    const int cx = w.o[0] + r / w.w[1];
-    for (int z = 0; z < w.w[2]; ++z) {
-      const int k = r * w.w[2] + z;
-      const int c3[3] = {cx, cy, w.o[2] + z};
-      const long long c = pk::cell_index(c3, mask, lm);
-      for (int f = 0; f < nf; ++f) {
-        const T v = lds[f * kWCap + k];
-        if (v != T(0)) pk::atomic_add(dst + f * M + c, v);
+  for (int base = 0; base < w.vol; base += kBatch * kThreads) {
+    T v[kBatch][3];
+    long long c[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = base + j * kThreads + threadIdx.x;
+      c[j] = -1;
+      if (k < w.vol) {
+        c[j] = win_cell(w, k, mask, lm);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+          if (f < nf) v[j][f] = lds[f * kWCap + k];
       }
     }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (c[j] < 0) continue;
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+        if (f < nf && v[j][f] != T(0)) pk::atomic_add(dst + f * M + c[j], v[j][f]);
+    }
   }
+}
+
+// Counts tiles that did not fit their window (they took the direct path).
+__device__ __forceinline__ void count_overflow(const Window& w, unsigned* counter) {
+  if (!w.fits && counter && threadIdx.x == 0) atomicAdd(counter, 1u);
 }
 
 }  // namespace tk
