@@ -31,23 +31,33 @@ __device__ __forceinline__ void load_slots(Slots<T>& sl, const TileGeom& tg, int
   for (int k = 0; k < kPer; ++k) sl.ok[k] = tk::tile_particle(tg, lp, k, sl.idx[k], sl.n[k]);
 }
 
-// Paint weight w (times per-field values v[f]) of stencil s into the window
-// (LDS atomics) or, for tiles that do not fit, straight into the mesh.
-template <typename T, int NF>
-__device__ __forceinline__ void paint_stencil(const Stencil<T>& s, const T v[NF], const Window& w,
-                                              T* lds, int lm, T* __restrict__ mesh, long long M) {
+// Paints weight w times value v of stencil s into the FP64 window (LDS
+// atomics) or, for tiles that do not fit, straight into the mesh.
+template <typename T>
+__device__ __forceinline__ void paint_stencil(const Stencil<T>& s, T v, const Window& w,
+                                              tk::Acc* acc, int lm, T* __restrict__ mesh) {
   if (w.fits) {
     for_corners_xyz(s, [&](int cx, int cy, int cz, T wt, T, T, T) {
-      const int k = tk::win_index(w, cx, cy, cz);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) atomicAdd(&lds[f * kWCap + k], wt * v[f]);
+      atomicAdd(&acc[tk::win_index(w, cx, cy, cz)], tk::Acc(wt) * tk::Acc(v));
     });
   } else {
-    for_corners(s, lm, [&](long long c, T wt, T, T, T) {
-#pragma unroll
-      for (int f = 0; f < NF; ++f) atomic_add(mesh + f * M + c, wt * v[f]);
-    });
+    for_corners(s, lm, [&](long long c, T wt, T, T, T) { atomic_add(mesh + c, wt * v); });
   }
+}
+
+// Zeroes the window, paints one value per valid slot, flushes the window.
+// Every thread of the block calls it (it holds barriers).
+template <typename T>
+__device__ __forceinline__ void paint_pass(const Stencil<T> st[kPer], const bool ok[kPer],
+                                           const T v[kPer], const Window& w, tk::Acc* acc,
+                                           int lm, T* __restrict__ mesh) {
+  if (w.fits) tk::win_zero(w, acc);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (ok[k]) paint_stencil<T>(st[k], v[k], w, acc, lm, mesh);
+  __syncthreads();
+  if (w.fits) tk::win_flush(w, acc, lm, mesh);
 }
 
 // F_f = sum over corners of W g_f, from the window or from the mesh.
@@ -99,7 +109,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_t(const T* __restrict__ d, long long P, int lp,
                                                       TileGeom tg, Grid<T> g,
                                                       T* __restrict__ rho, unsigned* __restrict__ ovf) {
-  __shared__ T lds[kWCap];
+  __shared__ tk::Acc acc[kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
   load_slots(sl, tg, lp);
@@ -113,14 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_paint_t(const T* __restrict__ d, l
   }
   Window w = window_of(bs, st, sl.ok);
   tk::count_overflow(w, ovf);
-  if (w.fits) tk::win_zero(w, 1, lds);
-  __syncthreads();
-  const T one[1] = {T(1)};
+  T one[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w, lds, g.lm, rho, 0);
-  __syncthreads();
-  if (w.fits) tk::win_flush(w, lds, 1, g.lm, rho, 0);
+  for (int k = 0; k < kPer; ++k) one[k] = T(1);
+  paint_pass<T>(st, sl.ok, one, w, acc, g.lm, rho);
 }
 
 // g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart.
@@ -130,12 +136,12 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_t(const T* __restrict__ 
                                                           long long P, int lp, TileGeom tg,
                                                           Grid<T> g, T* __restrict__ out,
                                                           long long M, unsigned* __restrict__ ovf) {
-  __shared__ T lds[3 * kWCap];
+  __shared__ tk::Acc acc[kWCap];
   __shared__ BoxShared bs;
   Slots<T> sl;
   load_slots(sl, tg, lp);
   Stencil<T> st[kPer];
-  T vv[kPer][3];
+  T vv[kPer][3] = {};
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (!sl.ok[k]) continue;
@@ -148,13 +154,15 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_t(const T* __restrict__ 
   }
   Window w = window_of(bs, st, sl.ok);
   tk::count_overflow(w, ovf);
-  if (w.fits) tk::win_zero(w, 3, lds);
-  __syncthreads();
+  // One field at a time through one FP64 window (32 KiB of LDS per block).
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    if (f > 0) __syncthreads();  // the previous flush has read the window
+    T vf[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if (sl.ok[k]) paint_stencil<T, 3>(st[k], vv[k], w, lds, g.lm, out, M);
-  __syncthreads();
-  if (w.fits) tk::win_flush(w, lds, 3, g.lm, out, M);
+    for (int k = 0; k < kPer; ++k) vf[k] = vv[k][f];
+    paint_pass<T>(st, sl.ok, vf, w, acc, g.lm, out + f * M);
+  }
 }
 
 // Fused step: readout of g at d_cur, kick p += kick F; drift
@@ -164,7 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_pm_step_t(
     const T* __restrict__ dcur, T* __restrict__ p, const T* __restrict__ g, long long M, T kick,
     T drift, T* __restrict__ dnext, T* __restrict__ rho, long long P, int lp, TileGeom tg,
     Grid<T> gr, unsigned* __restrict__ ovf) {
-  __shared__ T lds[3 * kWCap];
+  __shared__ __align__(16) unsigned char smem[tk::lds_bytes<T>(3)];
+  T* lds = reinterpret_cast<T*>(smem);
+  tk::Acc* acc = reinterpret_cast<tk::Acc*>(smem);
   __shared__ BoxShared bs;
   Slots<T> sl;
   load_slots(sl, tg, lp);
@@ -197,14 +207,10 @@ __global__ __launch_bounds__(kThreads) void k_pm_step_t(
   }
   Window w2 = window_of(bs, st, sl.ok);
   tk::count_overflow(w2, ovf);
-  if (w2.fits) tk::win_zero(w2, 1, lds);
-  __syncthreads();
-  const T one[1] = {T(1)};
+  T one[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w2, lds, gr.lm, rho, 0);
-  __syncthreads();
-  if (w2.fits) tk::win_flush(w2, lds, 1, gr.lm, rho, 0);
+  for (int k = 0; k < kPer; ++k) one[k] = T(1);
+  paint_pass<T>(st, sl.ok, one, w2, acc, gr.lm, rho);
 }
 
 // Last kick (readout of g at d), then RSD and the data-grid paint.
@@ -214,7 +220,9 @@ __global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T
                                                       T kick, Grid<T> gm, Rsd<T> rsd, Grid<T> gd,
                                                       T* __restrict__ rho_d, long long P, int lp,
                                                       TileGeom tg, unsigned* __restrict__ ovf) {
-  __shared__ T lds[3 * kWCap];
+  __shared__ __align__(16) unsigned char smem[tk::lds_bytes<T>(3)];
+  T* lds = reinterpret_cast<T*>(smem);
+  tk::Acc* acc = reinterpret_cast<tk::Acc*>(smem);
   __shared__ BoxShared bs;
   Slots<T> sl;
   load_slots(sl, tg, lp);
@@ -246,14 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_final_t(const T* __restrict__ d, T
   }
   Window w2 = window_of(bs, st, sl.ok);
   tk::count_overflow(w2, ovf);
-  if (w2.fits) tk::win_zero(w2, 1, lds);
-  __syncthreads();
-  const T one[1] = {T(1)};
+  T one[kPer];
 #pragma unroll
-  for (int k = 0; k < kPer; ++k)
-    if (sl.ok[k]) paint_stencil<T, 1>(st[k], one, w2, lds, gd.lm, rho_d, 0);
-  __syncthreads();
-  if (w2.fits) tk::win_flush(w2, lds, 1, gd.lm, rho_d, 0);
+  for (int k = 0; k < kPer; ++k) one[k] = T(1);
+  paint_pass<T>(st, sl.ok, one, w2, acc, gd.lm, rho_d);
 }
 
 // Adjoint of RSD + data paint (see k_data_adjoint), data-grid window.

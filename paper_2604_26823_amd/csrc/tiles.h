@@ -5,12 +5,16 @@
 // their lattice neighbours, the CIC stencils of a tile fall inside a small
 // Eulerian box.  The workgroup finds that box (LDS min/max), and then
 //   * paints into an LDS window with LDS atomics and flushes each non-zero
-//     window cell to HBM with one global atomic, one window row per lane so
-//     a wavefront's atomics land on 64 different cache lines;
+//     window cell to HBM with one global atomic, consecutive lanes on
+//     consecutive cells so a wavefront's atomics fall on few cache lines;
 //   * or reads mesh fields for gathers from a window loaded with coalesced
 //     row loads, so every CIC corner read is an LDS read.
+// Paint windows accumulate in FP64 for both precisions: on gfx950 the LDS
+// FP64 atomic add (ds_add_f64) sustains about twenty times the lane rate of
+// the FP32 one (ds_add_f32), which executes close to one lane at a time, and
+// the FP64 sum is rounded to the mesh precision once, at the flush.
 // A tile whose box exceeds the window capacity (strongly clustered regions)
-// takes the direct global path for that call; results are the same.
+// takes the direct global path for that call; results agree to rounding.
 #pragma once
 
 #include <climits>
@@ -23,6 +27,18 @@ namespace tk {
 constexpr int kThreads = 256;
 constexpr int kPer = 2;  // particles per thread
 constexpr int kWCap = 4096;  // window cells per field
+
+// FP64 paint-window accumulator.
+using Acc = double;
+
+// Bytes of a kernel's LDS block holding ng gather fields of T, or one paint
+// window of Acc, whichever is larger (the two phases reuse the block).
+template <typename T>
+constexpr unsigned lds_bytes(int ng) {
+  const unsigned g = (unsigned)(ng * kWCap) * (unsigned)sizeof(T);
+  const unsigned p = (unsigned)kWCap * (unsigned)sizeof(Acc);
+  return g > p ? g : p;
+}
 
 // Tile shape (tx, ty, tz) and tile counts per axis for a side-n lattice.
 struct TileGeom {
@@ -178,23 +194,21 @@ __device__ __forceinline__ void win_load(const Window& w, const T* __restrict__ 
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void win_zero(const Window& w, int nf, T* lds) {
-  for (int f = 0; f < nf; ++f)
-    for (int k = threadIdx.x; k < w.vol; k += kThreads) lds[f * kWCap + k] = T(0);
+__device__ __forceinline__ void win_zero(const Window& w, Acc* acc) {
+  for (int k = threadIdx.x; k < w.vol; k += kThreads) acc[k] = Acc(0);
 }
 
-// Adds the non-zero window cells of nf fields into the mesh (stride M) with
+// Adds the non-zero cells of one FP64 window into the mesh of type T with
 // global atomics.  Consecutive lanes take consecutive window cells (rows run
 // along z), so a wavefront's atomics fall on a few cache lines: the memory
 // system applies all lanes that hit one line in a single operation, which is
 // what makes the flush cheap compared with one atomic stream per particle.
 template <typename T>
-__device__ __forceinline__ void win_flush(const Window& w, const T* lds, int nf, int lm,
-                                          T* __restrict__ dst, long long M) {
+__device__ __forceinline__ void win_flush(const Window& w, const Acc* acc, int lm,
+                                          T* __restrict__ dst) {
   const int mask = (1 << lm) - 1;
   for (int base = 0; base < w.vol; base += kBatch * kThreads) {
-    T v[kBatch][3];
+    T v[kBatch];
     long long c[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
@@ -202,18 +216,12 @@ __device__ __forceinline__ void win_flush(const Window& w, const T* lds, int nf,
       c[j] = -1;
       if (k < w.vol) {
         c[j] = win_cell(w, k, mask, lm);
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-          if (f < nf) v[j][f] = lds[f * kWCap + k];
+        v[j] = static_cast<T>(acc[k]);
       }
     }
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      if (c[j] < 0) continue;
-#pragma unroll
-      for (int f = 0; f < 3; ++f)
-        if (f < nf && v[j][f] != T(0)) pk::atomic_add(dst + f * M + c[j], v[j][f]);
-    }
+    for (int j = 0; j < kBatch; ++j)
+      if (c[j] >= 0 && v[j] != T(0)) pk::atomic_add(dst + c[j], v[j]);
   }
 }
 
