@@ -105,7 +105,7 @@ class Engine final : public EngineBase {
     vbuf_ = c.take<T>(P_);
     tbuf_ = c.take<T>(P_);
     binc_ = c.take<uint32_t>(256);
-    ovf_ = c.take<uint32_t>(kOvfSlots);
+    tstat_ = c.take<unsigned long long>(kStatPerKernel * kStatKernels);
     dbg_idx_[0] = c.take<uint32_t>(P_);
     dbg_key_[0] = c.take<T>(P_);
     dbg_idx_[1] = c.take<uint32_t>(Hp_);
@@ -296,16 +296,30 @@ class Engine final : public EngineBase {
 
   void timing(bool enable) override {
     if (enable) {
-      ek_fill_u32(ovf_, 0u, kOvfSlots);
+      ek_fill_u32(reinterpret_cast<uint32_t*>(tstat_), 0u, 2 * kStatPerKernel * kStatKernels);
     }
     timer_.enable(enable);
   }
   std::string timing_report() override {
     std::string r = timer_.report();
-    uint32_t cnt[kOvfSlots];
-    IC_HIP(hipMemcpyAsync(cnt, ovf_, sizeof(cnt), hipMemcpyDeviceToHost, st_));
+    std::vector<unsigned long long> cnt(kStatPerKernel * kStatKernels);
+    IC_HIP(hipMemcpyAsync(cnt.data(), tstat_, cnt.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, st_));
     IC_HIP(hipStreamSynchronize(st_));
-    for (int k = 0; k < 6; ++k) r += std::string(kOvfNames[k]) + " " + std::to_string(cnt[k]) + " 0 0\n";
+    // Rows "tiles_<kernel> windows 0 cells", "tiles_direct_<kernel> tiles 0 0"
+    // and "tiles_max_<kernel> cells 0 0".
+    for (int k = 0; k < kStatKernels; ++k) {
+      unsigned long long v[4] = {0, 0, 0, 0};
+      for (int j = 0; j < tk::kStatSlots; ++j) {
+        const unsigned long long* s = cnt.data() + k * kStatPerKernel + tk::kStatWords * j;
+        for (int q = 0; q < 3; ++q) v[q] += s[q];
+        v[3] = std::max(v[3], s[3]);
+      }
+      const std::string nm = kStatNames[k];
+      r += "tiles_" + nm + " " + std::to_string(v[0]) + " 0 " + std::to_string(v[2]) + "\n";
+      r += "tiles_direct_" + nm + " " + std::to_string(v[1]) + " 0 0\n";
+      r += "tiles_max_" + nm + " " + std::to_string(v[3]) + " 0 0\n";
+    }
     return r;
   }
 
@@ -350,7 +364,9 @@ class Engine final : public EngineBase {
   }
 
   // Window-overflow counter of a tiled kernel (only while timing is on).
-  unsigned* ovf(int k) const { return timer_.enabled() ? ovf_ + k : nullptr; }
+  unsigned long long* ovf(int k) const {
+    return timer_.enabled() ? tstat_ + kStatPerKernel * k : nullptr;
+  }
 
   T* dslot(int n) const { return dtape_ + (long long)n * 3 * P_; }
   T* gslot(int n) const { return tape_forces_ ? gtape_ + (long long)n * 3 * M_ : gtape_; }
@@ -720,12 +736,12 @@ class Engine final : public EngineBase {
   double *part_, *scal_;
   T *hist_S_, *hist_Y_, *dir_, *strial_, *gtrial_;
   uint64_t *keys_, *keys2_;
-  uint32_t *vals_, *vals2_, *small_, *shist_, *binc_, *ovf_;
-  static constexpr int kOvfSlots = 8;
-  static constexpr const char* kOvfNames[6] = {"tiles_direct_paint", "tiles_direct_pm_step",
-                                               "tiles_direct_final", "tiles_direct_data_adjoint",
-                                               "tiles_direct_paint_vec",
-                                               "tiles_direct_force_adjoint"};
+  uint32_t *vals_, *vals2_, *small_, *shist_, *binc_;
+  unsigned long long* tstat_;  // per tiled kernel: tk::kStatSlots groups of 4 counters
+  static constexpr int kStatKernels = 6;
+  static constexpr int kStatPerKernel = tk::kStatWords * tk::kStatSlots;
+  static constexpr const char* kStatNames[kStatKernels] = {
+      "paint", "pm_step", "final", "data_adjoint", "paint_vec", "force_adjoint"};
   T *vbuf_, *tbuf_;
   uint32_t* dbg_idx_[2];
   T* dbg_key_[2];

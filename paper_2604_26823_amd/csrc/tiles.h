@@ -26,7 +26,22 @@ namespace tk {
 
 constexpr int kThreads = 256;
 constexpr int kPer = 2;  // particles per thread
-constexpr int kWCap = 4096;  // window cells per field
+#ifndef IC_TILE_GCAP
+#define IC_TILE_GCAP 2048
+#endif
+#ifndef IC_TILE_PCAP
+#define IC_TILE_PCAP 4096
+#endif
+#ifndef IC_TILE_WAVES
+#define IC_TILE_WAVES 1
+#endif
+// Window capacities in cells: per field for gather windows (mesh type), and
+// for the one FP64 paint window.  A direct-path gather costs little more than
+// a window gather while a direct-path paint costs one global atomic per
+// corner, so paint windows get the larger capacity.
+constexpr int kGCap = IC_TILE_GCAP;
+constexpr int kPCap = IC_TILE_PCAP;
+constexpr int kWaves = IC_TILE_WAVES;  // minimum waves per SIMD asked of the compiler
 
 // FP64 paint-window accumulator.
 using Acc = double;
@@ -35,8 +50,8 @@ using Acc = double;
 // window of Acc, whichever is larger (the two phases reuse the block).
 template <typename T>
 constexpr unsigned lds_bytes(int ng) {
-  const unsigned g = (unsigned)(ng * kWCap) * (unsigned)sizeof(T);
-  const unsigned p = (unsigned)kWCap * (unsigned)sizeof(Acc);
+  const unsigned g = (unsigned)(ng * kGCap) * (unsigned)sizeof(T);
+  const unsigned p = (unsigned)kPCap * (unsigned)sizeof(Acc);
   return g > p ? g : p;
 }
 
@@ -93,7 +108,17 @@ struct Window {
   int w[3];
   int vol;
   bool fits;
+  unsigned long long mz, my;  // ceil(2^32 / w[2]), ceil(2^32 / w[1])
 };
+
+// floor(k / d) as (k * ceil(2^32 / d)) >> 32: exact whenever k * d < 2^32,
+// which holds for window indices and extents (both below 2^16).
+__device__ __forceinline__ unsigned long long div_magic(int d) {
+  return ((1ull << 32) + (unsigned long long)d - 1ull) / (unsigned long long)d;
+}
+__device__ __forceinline__ int div_by(int k, unsigned long long m) {
+  return (int)(((unsigned long long)(unsigned)k * m) >> 32);
+}
 
 struct BoxShared {
   int lo[3];
@@ -128,8 +153,9 @@ __device__ __forceinline__ void box_add_range(BoxShared& b, int lo[3], int hi[3]
   }
 }
 
-// Call after a barrier that follows all box_add calls.
-__device__ __forceinline__ Window box_window(const BoxShared& b) {
+// Window of the box, fitting when it holds at most cap cells.  Call after a
+// barrier that follows all box_add_range calls.
+__device__ __forceinline__ Window box_window(const BoxShared& b, int cap) {
   Window w;
   long long vol = 1;
   bool empty = false;
@@ -141,8 +167,10 @@ __device__ __forceinline__ Window box_window(const BoxShared& b) {
     w.w[a] = ext > 0 && ext < (1 << 20) ? static_cast<int>(ext) : 0;
     vol *= ext > 0 ? ext : 0;
   }
-  w.fits = !empty && vol <= kWCap;
+  w.fits = !empty && vol <= cap;
   w.vol = w.fits ? static_cast<int>(vol) : 0;
+  w.mz = w.fits ? div_magic(w.w[2]) : 0;
+  w.my = w.fits ? div_magic(w.w[1]) : 0;
   return w;
 }
 
@@ -153,33 +181,39 @@ __device__ __forceinline__ int win_index(const Window& w, int cx, int cy, int cz
 
 // Physical (wrapped) mesh index of window cell number k.
 __device__ __forceinline__ long long win_cell(const Window& w, int k, int mask, int lm) {
-  const int cz = w.o[2] + k % w.w[2];
-  const int t = k / w.w[2];
-  const int cy = w.o[1] + t % w.w[1];
-  const int cx = w.o[0] + t / w.w[1];
+  const int t = div_by(k, w.mz);
+  const int u = div_by(t, w.my);
+  const int cz = w.o[2] + (k - t * w.w[2]);
+  const int cy = w.o[1] + (t - u * w.w[1]);
+  const int cx = w.o[0] + u;
   const int c[3] = {cx, cy, cz};
   return pk::cell_index(c, mask, lm);
 }
 
-// Loads nf fields (stride M) of the window into lds[f * kWCap + k].  Each
-// thread issues the loads of kBatch cells before storing any of them, so the
+// Source pointers of NF mesh fields read through one window.
+template <typename T, int NF>
+struct Fields {
+  const T* p[NF];
+};
+
+// Loads NF fields of the window into lds[f * kGCap + k].  Each thread issues
+// the loads of kBatch cells (all fields) before storing any of them, so the
 // loads of a batch are in flight together instead of one at a time.
 constexpr int kBatch = 8;
 
-template <typename T>
-__device__ __forceinline__ void win_load(const Window& w, const T* __restrict__ src, long long M,
-                                         int nf, int lm, T* lds) {
+template <typename T, int NF>
+__device__ __forceinline__ void win_load(const Window& w, const Fields<T, NF>& src, int lm,
+                                         T* lds) {
   const int mask = (1 << lm) - 1;
   for (int base = 0; base < w.vol; base += kBatch * kThreads) {
-    T v[kBatch][4];
+    T v[kBatch][NF];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const int k = base + j * kThreads + threadIdx.x;
       if (k < w.vol) {
         const long long c = win_cell(w, k, mask, lm);
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
-          if (f < nf) v[j][f] = src[f * M + c];
+        for (int f = 0; f < NF; ++f) v[j][f] = src.p[f][c];
       }
     }
 #pragma unroll
@@ -187,8 +221,7 @@ __device__ __forceinline__ void win_load(const Window& w, const T* __restrict__ 
       const int k = base + j * kThreads + threadIdx.x;
       if (k < w.vol) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f)
-          if (f < nf) lds[f * kWCap + k] = v[j][f];
+        for (int f = 0; f < NF; ++f) lds[f * kGCap + k] = v[j][f];
       }
     }
   }
@@ -225,9 +258,25 @@ __device__ __forceinline__ void win_flush(const Window& w, const Acc* acc, int l
   }
 }
 
-// Counts tiles that did not fit their window (they took the direct path).
-__device__ __forceinline__ void count_overflow(const Window& w, unsigned* counter) {
-  if (!w.fits && counter && threadIdx.x == 0) atomicAdd(counter, 1u);
+// Window statistics while kernel timing is on, spread over kStatSlots
+// groups of kStatWords counters (block b uses group b mod kStatSlots) so
+// blocks do not queue on one address: [0] windows, [1] windows that did not
+// fit (their tile took the direct path), [2] cells of the windows that fit,
+// [3] largest window asked for, in cells.
+constexpr int kStatSlots = 64;
+constexpr int kStatWords = 4;
+
+__device__ __forceinline__ void tile_stats(const Window& w, const BoxShared& b,
+                                           unsigned long long* stats) {
+  if (stats && threadIdx.x == 0) {
+    unsigned long long* s = stats + kStatWords * (blockIdx.x % kStatSlots);
+    long long vol = 1;
+    for (int a = 0; a < 3; ++a) vol *= (long long)b.hi[a] - (long long)b.lo[a] + 1;
+    atomicAdd(s, 1ull);
+    if (!w.fits) atomicAdd(s + 1, 1ull);
+    atomicAdd(s + 2, (unsigned long long)w.vol);
+    atomicMax(s + 3, (unsigned long long)(vol > 0 ? vol : 0));
+  }
 }
 
 }  // namespace tk
