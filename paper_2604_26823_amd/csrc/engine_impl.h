@@ -63,8 +63,11 @@ class Engine final : public EngineBase {
     ratio_ = nm_ / np_;
     P_ = (long long)np_ * np_ * np_;
     M_ = (long long)nm_ * nm_ * nm_;
-    Hp_ = (long long)np_ * np_ * (np_ / 2 + 1);
-    Hm_ = (long long)nm_ * nm_ * (nm_ / 2 + 1);
+    kpp_ = spectrum_pitch<T>(np_);
+    kpm_ = spectrum_pitch<T>(nm_);
+    Hp_ = (long long)np_ * np_ * kpp_;
+    Hm_ = (long long)nm_ * nm_ * kpm_;
+    Hq_ = (long long)np_ * np_ * (np_ / 2 + 1);
     tape_forces_ = p.tape_forces != 0;
     tg_ = tk::tile_geom(np_);
     const int m = std::max(1, p.lbfgs_m);
@@ -108,9 +111,9 @@ class Engine final : public EngineBase {
     tstat_ = c.take<unsigned long long>(kStatPerKernel * kStatKernels);
     dbg_idx_[0] = c.take<uint32_t>(P_);
     dbg_key_[0] = c.take<T>(P_);
-    dbg_idx_[1] = c.take<uint32_t>(Hp_);
-    dbg_key_[1] = c.take<T>(Hp_);
-    dbg_bin_ = c.take<uint32_t>(Hp_);
+    dbg_idx_[1] = c.take<uint32_t>(Hq_);
+    dbg_key_[1] = c.take<T>(Hq_);
+    dbg_bin_ = c.take<uint32_t>(Hq_);
     need_ = c.used();
     if (!ws) return;
     if (ws_bytes < need_) throw ApiError(IC_ERR_WORKSPACE, "workspace too small");
@@ -199,21 +202,23 @@ class Engine final : public EngineBase {
     hist_.clear();
   }
 
+  // Spectra cross the ABI in the contiguous n x n x (n/2+1) layout.
   void op_rfft(int grid, const void* x, void* xk) override {
     auto f = fa(grid);
-    cx<T>* out = static_cast<cx<T>*>(xk);
     {
       auto sc = timer_.scope("fft_r2c_z", 0);
-      fft_r2c_z<T>(f, static_cast<const T*>(x), T(1), nullptr, T(0), out);
+      fft_r2c_z<T>(f, static_cast<const T*>(x), T(1), nullptr, T(0), pool_);
     }
-    fft_y<T>(f, out, true);
-    fft_x<T>(f, out, out, true, T(1));
+    fft_y<T>(f, pool_, true);
+    fft_x<T>(f, pool_, pool_, true, T(1));
+    spectrum_pack<T>(f, pool_, static_cast<cx<T>*>(xk));
   }
 
   void op_irfft(int grid, const void* xk, void* x) override {
     auto f = fa(grid);
     const long long n3 = grid ? M_ : P_;
-    fft_x<T>(f, static_cast<const cx<T>*>(xk), pool_, false, T(1.0 / (double)n3));
+    spectrum_unpack<T>(f, static_cast<const cx<T>*>(xk), pool_);
+    fft_x<T>(f, pool_, pool_, false, T(1.0 / (double)n3));
     fft_y<T>(f, pool_, false);
     fft_c2r_z<T>(f, pool_, static_cast<T*>(x), T(1), nullptr, T(0));
   }
@@ -338,6 +343,7 @@ class Engine final : public EngineBase {
   FftArgs<T> fa(int grid) const {
     FftArgs<T> f;
     f.n = grid ? nm_ : np_;
+    f.kp = grid ? kpm_ : kpp_;
     f.tw = grid ? twm_ : twp_;
     f.wtab = wtab_;
     f.box = prob_.box;
@@ -720,7 +726,10 @@ class Engine final : public EngineBase {
   hipStream_t st_;
   Coeffs co_;
   int np_, nm_, S_, lp_, lm_, ratio_;
-  long long P_, M_, Hp_, Hm_;
+  long long P_, M_;
+  int kpp_ = 0, kpm_ = 0;  // stored half-spectrum row pitches (particle grid, mesh)
+  long long Hp_, Hm_;      // stored half-spectrum sizes (padded rows)
+  long long Hq_;           // half-spectrum modes of the particle grid, n^2 (n/2+1)
   bool tape_forces_;
   tk::TileGeom tg_;
   int wtab_len_;

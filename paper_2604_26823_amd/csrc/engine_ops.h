@@ -86,19 +86,19 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
   const double kf = 2.0 * 3.14159265358979323846 / prob_.box;
   const double kmax = std::sqrt(3.0) * 3.14159265358979323846 * np_ / prob_.box;
   const double dk = (kmax - prob_.rom_kmin) / nbins;
-  const unsigned G = grid_for(Hp_, kThreads);
+  const unsigned G = grid_for(Hq_, kThreads);
   const int vbits = 8 * sizeof(T);
-  rk::k_mode_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, static_cast<T>(1.0 / n3h), kf,
+  rk::k_mode_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, kpp_, static_cast<T>(1.0 / n3h), kf,
                                               prob_.rom_kmin, dk, nbins, vbuf_, keys_, vals_,
-                                              small_, Hp_);
+                                              small_, Hq_);
   IC_LAUNCHED();
-  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hp_, vbits, st_);
-  sk::k_gather_u32_key<<<G, kThreads, 0, st_>>>(small_, vals_, keys_, Hp_);
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hq_, vbits, st_);
+  sk::k_gather_u32_key<<<G, kThreads, 0, st_>>>(small_, vals_, keys_, Hq_);
   IC_LAUNCHED();
-  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hp_, 8, st_);
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hq_, 8, st_);
   ek::k_fill_u32<<<1, 256, 0, st_>>>(binc_, 0u, 256);
   IC_LAUNCHED();
-  rk::k_bin_count<<<G, kThreads, 0, st_>>>(keys_, binc_, Hp_);
+  rk::k_bin_count<<<G, kThreads, 0, st_>>>(keys_, binc_, Hq_);
   IC_LAUNCHED();
   std::vector<uint32_t>& counts = bin_count_;
   IC_HIP(hipMemcpyAsync(counts.data(), binc_, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
@@ -130,8 +130,8 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
     sk::k_gather_u32_key<<<Gn, kThreads, 0, st_>>>(small_, vals_, keys_, n);
     IC_LAUNCHED();
     radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, 8, st_);
-    rk::k_fourier_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, dbg_idx_[1], tbuf_, vals_,
-                                                       static_cast<T>(n3h), n);
+    rk::k_fourier_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, kpp_, dbg_idx_[1], tbuf_,
+                                                       vals_, static_cast<T>(n3h), n);
     IC_LAUNCHED();
   }
   fft_x<T>(f, Z, Z, false, static_cast<T>(1.0 / (double)P_));

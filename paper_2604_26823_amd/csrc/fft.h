@@ -3,7 +3,9 @@
 // A 3D real transform of an n^3 cube is three axis passes: a real-to-complex
 // pass along the contiguous z axis (half-length complex FFT plus the
 // even/odd split), and complex passes along y and x over the half spectrum
-// [n][n][n/2+1] (numpy rfftn layout).  The x pass is the last forward axis
+// [n][n][n/2+1], stored with each z row padded to kp >= n/2+1 entries so
+// that rows start on 128-byte boundaries and the strided passes move whole
+// cache lines (the pad entries are never read).  The x pass is the last forward axis
 // and the first inverse one, so k-space multipliers are applied inside it:
 // one kernel runs the forward x FFT, multiplies by m multipliers and runs m
 // inverse x FFTs (scatter), or the reverse for m inputs summed into one
@@ -36,9 +38,19 @@ struct MulSet {
   double scale[kMaxMul];
 };
 
+// Row pitch of the stored half spectrum: n/2+1 rounded up to a multiple of
+// 128 bytes.
+template <typename T>
+inline int spectrum_pitch(int n) {
+  const int q = 128 / static_cast<int>(sizeof(cx<T>));
+  const int k = n / 2 + 1;
+  return (k + q - 1) / q * q;
+}
+
 template <typename T>
 struct FftArgs {
   int n = 0;                    // grid side
+  int kp = 0;                   // stored row pitch of the half spectrum (spectrum_pitch)
   const cx<T>* tw = nullptr;    // device table exp(-2 pi i m / n), m < n
   const T* wtab = nullptr;      // whitening multiplier indexed by |k|^2 / kf^2 (particle grid)
   double box = 1.0;             // box side (for i k / k^2)
@@ -60,6 +72,12 @@ void fft_y(const FftArgs<T>& f, cx<T>* data, bool forward);
 // Complex FFT along x, out = scale * FFT(in); in may equal out.
 template <typename T>
 void fft_x(const FftArgs<T>& f, const cx<T>* in, cx<T>* out, bool forward, T scale);
+
+// Copies between the stored half spectrum and the contiguous n x n x (n/2+1) layout.
+template <typename T>
+void spectrum_pack(const FftArgs<T>& f, const cx<T>* stored, cx<T>* dense);
+template <typename T>
+void spectrum_unpack(const FftArgs<T>& f, const cx<T>* dense, cx<T>* stored);
 
 // Forward x FFT of in, then for each j < m: outs[j] = inverse x FFT of (mult_j * .).
 template <typename T>

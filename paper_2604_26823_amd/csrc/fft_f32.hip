@@ -8,6 +8,8 @@ template void fft_c2r_z<float>(const FftArgs<float>&, const cx<float>*, float*, 
                                const float*, float);
 template void fft_y<float>(const FftArgs<float>&, cx<float>*, bool);
 template void fft_x<float>(const FftArgs<float>&, const cx<float>*, cx<float>*, bool, float);
+template void spectrum_pack<float>(const FftArgs<float>&, const cx<float>*, cx<float>*);
+template void spectrum_unpack<float>(const FftArgs<float>&, const cx<float>*, cx<float>*);
 template void fft_x_scatter<float>(const FftArgs<float>&, const cx<float>*, cx<float>* const*,
                                    const MulSpec*, int);
 template void fft_x_gather<float>(const FftArgs<float>&, const cx<float>* const*,

@@ -8,6 +8,8 @@ template void fft_c2r_z<double>(const FftArgs<double>&, const cx<double>*, doubl
                                const double*, double);
 template void fft_y<double>(const FftArgs<double>&, cx<double>*, bool);
 template void fft_x<double>(const FftArgs<double>&, const cx<double>*, cx<double>*, bool, double);
+template void spectrum_pack<double>(const FftArgs<double>&, const cx<double>*, cx<double>*);
+template void spectrum_unpack<double>(const FftArgs<double>&, const cx<double>*, cx<double>*);
 template void fft_x_scatter<double>(const FftArgs<double>&, const cx<double>*, cx<double>* const*,
                                    const MulSpec*, int);
 template void fft_x_gather<double>(const FftArgs<double>&, const cx<double>* const*,

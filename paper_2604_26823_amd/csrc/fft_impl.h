@@ -198,7 +198,7 @@ __device__ __forceinline__ void load_table(cx<T>* dst, const cx<T>* __restrict__
 template <typename T, int N>
 __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
     const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
-    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines) {
+    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines, int kp) {
   using C = ZCfg<T, N>;
   constexpr int n = C::n;
   __shared__ cx<T> buf[C::LINES * C::LS];
@@ -227,7 +227,7 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
   fft_line<T, n, true>(lane, buf, lidx, tw, 2, load0, storeL);
   __syncthreads();
   if (!valid) return;
-  cx<T>* o = out + (size_t)line * (n + 1);
+  cx<T>* o = out + (size_t)line * kp;
   const T half = static_cast<T>(0.5);
   for (int k = lane; k <= n; k += C::TPL) {
     cx<T> zk = lb[k == n ? 0 : k];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
 template <typename T, int N>
 __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
     const cx<T>* __restrict__ in, T* __restrict__ out, T alpha, const T* __restrict__ aux,
-    T beta, const cx<T>* __restrict__ twg, int nlines) {
+    T beta, const cx<T>* __restrict__ twg, int nlines, int kp) {
   using C = ZCfg<T, N>;
   constexpr int n = C::n;
   __shared__ cx<T> buf[C::LINES * C::LS];
@@ -255,7 +255,7 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
   const int line = blockIdx.x * C::LINES + l;
   const bool valid = line < nlines;
   cx<T>* lb = buf + l * C::LS;
-  const cx<T>* src = in + (size_t)line * (n + 1);
+  const cx<T>* src = in + (size_t)line * kp;
   for (int k = lane; k <= n; k += C::TPL) {
     cx<T> v = valid ? src[k] : mkc<T>(0, 0);
     if (k == 0 || k == n) v.y = 0;  // the real transform ignores these imaginary parts
@@ -289,11 +289,12 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
 
 // ------------------------------------------------- strided C2C (y or x)
 // Line L of the batch starts at (L / group) * gstride + L % group and its
-// elements are estride apart.
+// elements are estride apart; lines with L mod vmod >= vcnt are row padding
+// and are skipped.
 template <typename T, int N, bool FWD>
 __global__ __launch_bounds__((SCfg<T, N>::THREADS)) void k_strided(
     const cx<T>* in, cx<T>* out, T scale, const cx<T>* __restrict__ twg, int nlines, int group,
-    long long gstride, long long estride) {
+    long long gstride, long long estride, int vmod, int vcnt) {
   using C = SCfg<T, N>;
   __shared__ cx<T> buf[N * C::LP];
   __shared__ cx<T> tw[N];
@@ -302,7 +303,7 @@ __global__ __launch_bounds__((SCfg<T, N>::THREADS)) void k_strided(
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
-  const bool valid = line < nlines;
+  const bool valid = line < nlines && (line % vmod) < vcnt;
   const long long base = (long long)(line / group) * gstride + (line % group);
   auto load0 = [&](int e) -> cx<T> { return valid ? in[base + e * estride] : mkc<T>(0, 0); };
   auto storeL = [&](int e, cx<T> v) {
@@ -349,7 +350,7 @@ template <typename T, int N>
 __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
     const cx<T>* __restrict__ in, OutPtrs<T> outs, MulSet ms, int m,
     const T* __restrict__ wtab, T L_over_2pi, const cx<T>* __restrict__ twg, int nlines,
-    int K) {
+    int K, int kp) {
   using C = FCfg<T, N>;
   __shared__ cx<T> A[N * C::LP];
   __shared__ cx<T> B[N * C::LP];
@@ -359,9 +360,9 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
-  const bool valid = line < nlines;
-  const long long stride = (long long)nlines;  // = N * K
-  const int ky = line / K, kz = line % K;
+  const int ky = line / kp, kz = line % kp;
+  const bool valid = line < nlines && kz < K;
+  const long long stride = (long long)nlines;  // = N * kp
   const int iy = wave_index(ky, N), iz = kz;
   const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
   auto lidx = [&](int e) { return e * C::LP + l; };
@@ -388,7 +389,7 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
 template <typename T, int N>
 __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
     InPtrs<T> ins, MulSet ms, int m, cx<T>* out, const T* __restrict__ wtab, T L_over_2pi,
-    const cx<T>* __restrict__ twg, int nlines, int K) {
+    const cx<T>* __restrict__ twg, int nlines, int K, int kp) {
   using C = FCfg<T, N>;
   __shared__ cx<T> A[N * C::LP];
   __shared__ cx<T> B[N * C::LP];
@@ -398,9 +399,9 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
-  const bool valid = line < nlines;
-  const long long stride = (long long)nlines;
-  const int ky = line / K, kz = line % K;
+  const int ky = line / kp, kz = line % kp;
+  const bool valid = line < nlines && kz < K;
+  const long long stride = (long long)nlines;  // = N * kp
   const int iy = wave_index(ky, N), iz = kz;
   const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
   auto lidx = [&](int e) { return e * C::LP + l; };
@@ -427,6 +428,22 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
     if (valid) out[line + e * stride] = v;
   };
   fft_line<T, N, false>(lane, B, lidx, tw, 1, load_A, store_o);
+}
+
+// ------------------------------------------------- layout conversion
+// Copies between the stored half spectrum (row pitch kp) and the contiguous
+// [n][n][n/2+1] layout; pack = stored -> contiguous.
+template <typename T, bool PACK>
+__global__ void k_spec_copy(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int K,
+                            int kp, long long H) {
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < H;
+       f += (long long)gridDim.x * blockDim.x) {
+    const long long s = (f / K) * kp + f % K;
+    if (PACK)
+      dst[f] = src[s];
+    else
+      dst[s] = src[f];
+  }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -467,7 +484,7 @@ void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<
     using C = fftk::ZCfg<T, N>;
     const int nlines = f.n * f.n;
     fftk::k_r2c_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        a, alpha, b, beta, out, f.tw, nlines);
+        a, alpha, b, beta, out, f.tw, nlines, f.kp);
   });
   IC_LAUNCHED();
 }
@@ -479,7 +496,7 @@ void fft_c2r_z(const FftArgs<T>& f, const cx<T>* in, T* out, T alpha, const T* a
     using C = fftk::ZCfg<T, N>;
     const int nlines = f.n * f.n;
     fftk::k_c2r_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        in, out, alpha, aux, beta, f.tw, nlines);
+        in, out, alpha, aux, beta, f.tw, nlines, f.kp);
   });
   IC_LAUNCHED();
 }
@@ -489,15 +506,15 @@ void fft_y(const FftArgs<T>& f, cx<T>* data, bool forward) {
   fftk::dispatch_n<T>(f.n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     using C = fftk::SCfg<T, N>;
-    const int K = N / 2 + 1;
-    const int nlines = N * K;
+    const int K = N / 2 + 1, kp = f.kp;
+    const int nlines = N * kp;
     const unsigned grid = blocks_for(nlines, C::LINES);
     if (forward)
       fftk::k_strided<T, N, true><<<grid, C::THREADS, 0, f.stream>>>(
-          data, data, T(1), f.tw, nlines, K, (long long)N * K, K);
+          data, data, T(1), f.tw, nlines, kp, (long long)N * kp, kp, kp, K);
     else
       fftk::k_strided<T, N, false><<<grid, C::THREADS, 0, f.stream>>>(
-          data, data, T(1), f.tw, nlines, K, (long long)N * K, K);
+          data, data, T(1), f.tw, nlines, kp, (long long)N * kp, kp, kp, K);
   });
   IC_LAUNCHED();
 }
@@ -507,16 +524,32 @@ void fft_x(const FftArgs<T>& f, const cx<T>* in, cx<T>* out, bool forward, T sca
   fftk::dispatch_n<T>(f.n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     using C = fftk::SCfg<T, N>;
-    const int K = N / 2 + 1;
-    const int nlines = N * K;
+    const int K = N / 2 + 1, kp = f.kp;
+    const int nlines = N * kp;
     const unsigned grid = blocks_for(nlines, C::LINES);
     if (forward)
       fftk::k_strided<T, N, true><<<grid, C::THREADS, 0, f.stream>>>(
-          in, out, scale, f.tw, nlines, nlines, 0, nlines);
+          in, out, scale, f.tw, nlines, nlines, 0, nlines, kp, K);
     else
       fftk::k_strided<T, N, false><<<grid, C::THREADS, 0, f.stream>>>(
-          in, out, scale, f.tw, nlines, nlines, 0, nlines);
+          in, out, scale, f.tw, nlines, nlines, 0, nlines, kp, K);
   });
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void spectrum_pack(const FftArgs<T>& f, const cx<T>* stored, cx<T>* dense) {
+  const int K = f.n / 2 + 1;
+  const long long H = (long long)f.n * f.n * K;
+  fftk::k_spec_copy<T, true><<<grid_for(H, 256), 256, 0, f.stream>>>(stored, dense, K, f.kp, H);
+  IC_LAUNCHED();
+}
+
+template <typename T>
+void spectrum_unpack(const FftArgs<T>& f, const cx<T>* dense, cx<T>* stored) {
+  const int K = f.n / 2 + 1;
+  const long long H = (long long)f.n * f.n * K;
+  fftk::k_spec_copy<T, false><<<grid_for(H, 256), 256, 0, f.stream>>>(dense, stored, K, f.kp, H);
   IC_LAUNCHED();
 }
 
@@ -531,9 +564,9 @@ void fft_x_scatter(const FftArgs<T>& f, const cx<T>* in, cx<T>* const* outs,
     constexpr int N = decltype(NC)::value;
     using C = fftk::FCfg<T, N>;
     const int K = N / 2 + 1;
-    const int nlines = N * K;
+    const int nlines = N * f.kp;
     fftk::k_x_scatter<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        in, op, ms, m, f.wtab, l2p, f.tw, nlines, K);
+        in, op, ms, m, f.wtab, l2p, f.tw, nlines, K, f.kp);
   });
   IC_LAUNCHED();
 }
@@ -549,9 +582,9 @@ void fft_x_gather(const FftArgs<T>& f, const cx<T>* const* ins, const MulSpec* s
     constexpr int N = decltype(NC)::value;
     using C = fftk::FCfg<T, N>;
     const int K = N / 2 + 1;
-    const int nlines = N * K;
+    const int nlines = N * f.kp;
     fftk::k_x_gather<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        ip, ms, m, out, f.wtab, l2p, f.tw, nlines, K);
+        ip, ms, m, out, f.wtab, l2p, f.tw, nlines, K, f.kp);
   });
   IC_LAUNCHED();
 }

@@ -58,11 +58,13 @@ __global__ void k_scatter_sorted(T* __restrict__ s, const uint32_t* __restrict__
     s[idx[j]] = tau[order[j]];
 }
 
-// Fourier space: for every half-spectrum mode f = (kx n + ky)(n/2+1) + kz,
-// amplitude |z| = |Z_f| * scale, descending key, and second key = bin for
-// matched modes (independent, |k| >= k_min) or 255.
+// Fourier space: for every half-spectrum mode f = (kx n + ky)(n/2+1) + kz
+// (stored at (kx n + ky) kp + kz), amplitude |z| = |Z_f| * scale, descending
+// key, and second key = bin for matched modes (independent, |k| >= k_min)
+// or 255.
 template <typename T>
-__global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, T scale, double kf, double kmin,
+__global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, int kp, T scale, double kf,
+                            double kmin,
                             double dk, int nbins, T* __restrict__ amp,
                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                             uint32_t* __restrict__ second, long long H) {
@@ -72,7 +74,7 @@ __global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, T scale, double 
     const int kz = static_cast<int>(f % K);
     const long long r = f / K;
     const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
-    const cx<T> z = Z[f];
+    const cx<T> z = Z[r * kp + kz];
     const T a = sqrt(z.x * z.x + z.y * z.y) * scale;
     amp[f] = a;
     keys[f] = sk::descending_key<T>(a);
@@ -129,7 +131,8 @@ __global__ void k_fourier_targets(const uint64_t* __restrict__ bins,
 // matched mode f = idx[i], with the target tau[order[i]]; modes of the kz = 0
 // and kz = n/2 planes also set their conjugate partner.
 template <typename T>
-__global__ void k_fourier_scatter(cx<T>* __restrict__ Z, int n, const uint32_t* __restrict__ idx,
+__global__ void k_fourier_scatter(cx<T>* __restrict__ Z, int n, int kp,
+                                  const uint32_t* __restrict__ idx,
                                   const T* __restrict__ tau, const uint32_t* __restrict__ order,
                                   T unscale, long long cnt) {
   const int K = n / 2 + 1;
@@ -137,16 +140,16 @@ __global__ void k_fourier_scatter(cx<T>* __restrict__ Z, int n, const uint32_t* 
        i += (long long)gridDim.x * blockDim.x) {
     const long long f = idx[i];
     const T t = tau[order[i]] * unscale;
-    const cx<T> z = Z[f];
+    const int kz = static_cast<int>(f % K);
+    const long long r = f / K;
+    const cx<T> z = Z[r * kp + kz];
     const T a = sqrt(z.x * z.x + z.y * z.y);
     const cx<T> v = a > T(0) ? mkc<T>(z.x * (t / a), z.y * (t / a)) : mkc<T>(t, T(0));
-    Z[f] = v;
-    const int kz = static_cast<int>(f % K);
+    Z[r * kp + kz] = v;
     if (kz == 0 || kz == n / 2) {
-      const long long r = f / K;
       const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
       const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
-      Z[((long long)cx_ * n + cy) * K + kz] = mkc<T>(v.x, -v.y);
+      Z[((long long)cx_ * n + cy) * kp + kz] = mkc<T>(v.x, -v.y);
     }
   }
 }

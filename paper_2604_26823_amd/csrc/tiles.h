@@ -55,11 +55,20 @@ constexpr unsigned lds_bytes(int ng) {
   return g > p ? g : p;
 }
 
-// Tile shape (tx, ty, tz) and tile counts per axis for a side-n lattice.
+// Tile shape (tx, ty, tz) and tile counts per axis for a side-n lattice,
+// with their base-2 logarithms (every extent is a power of two).
 struct TileGeom {
   int tx, ty, tz;
   int nx, ny, nz;
+  int ltx, lty, ltz;
+  int lnx, lny, lnz;
 };
+
+inline int tile_log2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
 
 inline TileGeom tile_geom(int n) {
   TileGeom t;
@@ -69,6 +78,12 @@ inline TileGeom tile_geom(int n) {
   t.nx = n / t.tx;
   t.ny = n / t.ty;
   t.nz = n / t.tz;
+  t.ltx = tile_log2(t.tx);
+  t.lty = tile_log2(t.ty);
+  t.ltz = tile_log2(t.tz);
+  t.lnx = tile_log2(t.nx);
+  t.lny = tile_log2(t.ny);
+  t.lnz = tile_log2(t.nz);
   return t;
 }
 
@@ -90,14 +105,13 @@ __device__ __forceinline__ int xcd_tile(int b, int count) {
 __device__ __forceinline__ bool tile_particle(const TileGeom& tg, int lp, int k, int idx[3],
                                               long long& n) {
   const int l = threadIdx.x + k * kThreads;
-  const int cnt = tg.tx * tg.ty * tg.tz;
-  if (l >= cnt) return false;
-  const int lz = l % tg.tz, ly = (l / tg.tz) % tg.ty, lx = l / (tg.tz * tg.ty);
+  if (l >> (tg.ltx + tg.lty + tg.ltz)) return false;
+  const int lz = l & (tg.tz - 1), ly = (l >> tg.ltz) & (tg.ty - 1), lx = l >> (tg.ltz + tg.lty);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int bz = b % tg.nz, by = (b / tg.nz) % tg.ny, bx = b / (tg.nz * tg.ny);
-  idx[0] = bx * tg.tx + lx;
-  idx[1] = by * tg.ty + ly;
-  idx[2] = bz * tg.tz + lz;
+  const int bz = b & (tg.nz - 1), by = (b >> tg.lnz) & (tg.ny - 1), bx = b >> (tg.lnz + tg.lny);
+  idx[0] = (bx << tg.ltx) + lx;
+  idx[1] = (by << tg.lty) + ly;
+  idx[2] = (bz << tg.ltz) + lz;
   n = ((long long)idx[0] << (2 * lp)) | ((long long)idx[1] << lp) | (long long)idx[2];
   return true;
 }
@@ -108,16 +122,19 @@ struct Window {
   int w[3];
   int vol;
   bool fits;
-  unsigned long long mz, my;  // ceil(2^32 / w[2]), ceil(2^32 / w[1])
+  unsigned mz, my;  // division magics of w[2] and w[1] (div_magic)
 };
 
-// floor(k / d) as (k * ceil(2^32 / d)) >> 32: exact whenever k * d < 2^32,
-// which holds for window indices and extents (both below 2^16).
-__device__ __forceinline__ unsigned long long div_magic(int d) {
-  return ((1ull << 32) + (unsigned long long)d - 1ull) / (unsigned long long)d;
+// floor(k / d) for d >= 2 as the high word of k * ceil(2^32 / d): exact
+// whenever k * d < 2^32, which holds for window indices and extents (both
+// below 2^16).  ceil(2^32 / d) is computed in FP64, exact because 2^32 / d
+// is either an integer or at least 1/d away from one.  d = 1 maps to 0 and
+// is handled by div_by.
+__device__ __forceinline__ unsigned div_magic(int d) {
+  return d > 1 ? static_cast<unsigned>(ceil(4294967296.0 / static_cast<double>(d))) : 0u;
 }
-__device__ __forceinline__ int div_by(int k, unsigned long long m) {
-  return (int)(((unsigned long long)(unsigned)k * m) >> 32);
+__device__ __forceinline__ int div_by(int k, unsigned m) {
+  return m ? static_cast<int>(__umulhi(static_cast<unsigned>(k), m)) : k;
 }
 
 struct BoxShared {
@@ -179,15 +196,15 @@ __device__ __forceinline__ int win_index(const Window& w, int cx, int cy, int cz
   return ((cx - w.o[0]) * w.w[1] + (cy - w.o[1])) * w.w[2] + (cz - w.o[2]);
 }
 
-// Physical (wrapped) mesh index of window cell number k.
-__device__ __forceinline__ long long win_cell(const Window& w, int k, int mask, int lm) {
+// Physical (wrapped) mesh index of window cell number k (meshes have at
+// most 2^30 cells, so 32 bits hold it).
+__device__ __forceinline__ unsigned win_cell(const Window& w, int k, int mask, int lm) {
   const int t = div_by(k, w.mz);
   const int u = div_by(t, w.my);
-  const int cz = w.o[2] + (k - t * w.w[2]);
-  const int cy = w.o[1] + (t - u * w.w[1]);
-  const int cx = w.o[0] + u;
-  const int c[3] = {cx, cy, cz};
-  return pk::cell_index(c, mask, lm);
+  const unsigned cz = static_cast<unsigned>(w.o[2] + (k - t * w.w[2])) & mask;
+  const unsigned cy = static_cast<unsigned>(w.o[1] + (t - u * w.w[1])) & mask;
+  const unsigned cx = static_cast<unsigned>(w.o[0] + u) & mask;
+  return (cx << (2 * lm)) | (cy << lm) | cz;
 }
 
 // Source pointers of NF mesh fields read through one window.
@@ -207,14 +224,15 @@ __device__ __forceinline__ void win_load(const Window& w, const Fields<T, NF>& s
   const int mask = (1 << lm) - 1;
   for (int base = 0; base < w.vol; base += kBatch * kThreads) {
     T v[kBatch][NF];
+    // Cells past the window end load the last window cell (in bounds) and
+    // are not stored, so the loads need no branches and stay in flight
+    // together.
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      const int k = base + j * kThreads + threadIdx.x;
-      if (k < w.vol) {
-        const long long c = win_cell(w, k, mask, lm);
+      const int k = min(base + j * kThreads + static_cast<int>(threadIdx.x), w.vol - 1);
+      const unsigned c = win_cell(w, k, mask, lm);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[j][f] = src.p[f][c];
-      }
+      for (int f = 0; f < NF; ++f) v[j][f] = src.p[f][c];
     }
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
@@ -242,19 +260,19 @@ __device__ __forceinline__ void win_flush(const Window& w, const Acc* acc, int l
   const int mask = (1 << lm) - 1;
   for (int base = 0; base < w.vol; base += kBatch * kThreads) {
     T v[kBatch];
-    long long c[kBatch];
+    unsigned c[kBatch];
+    // Reads past the window end are clamped to its last cell and dropped.
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = min(base + j * kThreads + static_cast<int>(threadIdx.x), w.vol - 1);
+      c[j] = win_cell(w, k, mask, lm);
+      v[j] = static_cast<T>(acc[k]);
+    }
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const int k = base + j * kThreads + threadIdx.x;
-      c[j] = -1;
-      if (k < w.vol) {
-        c[j] = win_cell(w, k, mask, lm);
-        v[j] = static_cast<T>(acc[k]);
-      }
+      if (k < w.vol && v[j] != T(0)) pk::atomic_add(dst + c[j], v[j]);
     }
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j)
-      if (c[j] >= 0 && v[j] != T(0)) pk::atomic_add(dst + c[j], v[j]);
   }
 }
 
