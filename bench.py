@@ -9,17 +9,26 @@ shaped synthetic workload (c3).  The metric is gradient evaluations per
 second: all loss + gradient evaluations made in the K timed steps divided by
 their wall time, inputs already resident in HBM.
 
-Also reported: the same loop with the FP64 instantiation of the kernels, the
-per-kernel HIP-event timing of a separate K-step pass (dominant kernel's
-algorithmic HBM bandwidth against the 8 TB/s peak), and the FP64 CPU oracle's
-rate estimated from a bounded sample on the host cores.
+Also reported: the same loop with the FP64 instantiation of the kernels; a
+per-kernel HIP-event table from a profiling pass run before the timed region;
+the roofline of the dominant kernel (largest share of that table), whose
+launches are timed with HIP events on the library stream during the timed
+region itself (algorithmic bytes per launch / average launch time, against
+the 8 TB/s HBM peak), with its measured HBM traffic when a hardware-counter
+summary taken on the current sources is present under profiles/; the FP64 CPU
+oracle's rate estimated from a bounded sample on the host cores; and one
+timing of a 256^3 FP32 real FFT round trip through torch.fft (hipFFT/rocFFT)
+beside the same round trip through this library's passes, for comparison
+only.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
-                       [--no-fp64] [--no-cpu-baseline]
+                       [--no-fp64] [--no-cpu-baseline] [--no-fft-compare]
+                       [--profile-steps P] [--copy-mib N]
 """
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -87,40 +96,102 @@ def run_steps(ctx, s, g, L, first, k, rom_every):
     return L, evals, roms
 
 
-def timed_loop(ctx, s, steps, warmup, rom_every):
+def kernel_rows(ctx):
+    """Kernel rows of the timing report (tile-window statistics dropped)."""
+    return [r for r in ctx.timing_report() if not r["name"].startswith("tiles_")]
+
+
+def timed_loop(ctx, s, steps, warmup, rom_every, profile_steps=0):
+    """Warmup, an optional all-kernel profiling pass, then the timed steps
+    with the dominant kernel's launches timed live (FP32 context only)."""
     import torch
     L, g, _ = ctx.loss_and_grad(s)
     L, _, _ = run_steps(ctx, s, g, L, 0, warmup, rom_every)
+    first = warmup
+    table = dom = None
+    if profile_steps:
+        ctx.timing(True)
+        L, _, _ = run_steps(ctx, s, g, L, first, profile_steps, rom_every)
+        table = kernel_rows(ctx)
+        ctx.timing(False)
+        first += profile_steps
+        dom = max(table, key=lambda r: r["ms"])["name"]
+        ctx.timing_only(dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    L, evals, roms = run_steps(ctx, s, g, L, warmup, steps, rom_every)
+    L, evals, roms = run_steps(ctx, s, g, L, first, steps, rom_every)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dict(seconds=dt, evals=evals, roms=roms, loss=L, g=g)
+    live = None
+    if dom is not None:
+        live = [r for r in kernel_rows(ctx) if r["name"] == dom][0]
+        ctx.timing(False)
+    return dict(seconds=dt, evals=evals, roms=roms, loss=L, g=g, table=table, live=live)
 
 
-def kernel_table(ctx, s, g, L, first, steps, rom_every):
-    ctx.timing(True)
-    run_steps(ctx, s, g, L, first, steps, rom_every)
-    rows = ctx.timing_report()
-    ctx.timing(False)
-    return rows
+def stored_traffic(kernel, dtype_tag):
+    """HBM bytes per launch of a kernel from the hardware-counter summary in
+    profiles/, or None when there is none or it was taken on other sources."""
+    from paper_2604_26823_amd import build
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_c3_%s.txt" % dtype_tag)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    text = open(path).read()
+    m = re.search(r"^sources_sha256 (\w+)$", text, re.M)
+    if not m or m.group(1) != build.sources_digest():
+        return None, "counter summary taken on other sources"
+    m = re.search(r"^kernel %s \S+ .* hbm_bytes_per_launch (\S+)$" % re.escape(kernel), text,
+                  re.M)
+    if not m:
+        return None, "kernel not in the counter summary"
+    return float(m.group(1)), os.path.relpath(path, ROOT)
 
 
-def roofline(rows):
-    """Dominant kernel (largest total time) and its algorithmic bandwidth."""
-    tot = sum(r["ms"] for r in rows)
-    dom = max(rows, key=lambda r: r["ms"])
-    avg_ms = dom["ms"] / dom["count"]
-    gbs = dom["bytes"] / (avg_ms * 1e-3) / 1e9
-    table = {r["name"]: dict(launches=r["count"], total_ms=round(r["ms"], 3),
-                             avg_us=round(1e3 * r["ms"] / r["count"], 2),
-                             gbs=round(r["bytes"] / (r["ms"] / r["count"] * 1e-3) / 1e9, 1)
-                             if r["bytes"] > 0 else None,
-                             share=round(r["ms"] / tot, 4)) for r in rows}
-    return dict(bound="hbm", kernel=dom["name"], achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                avg_us=round(1e3 * avg_ms, 2), bytes_per_launch=dom["bytes"]), table
+def roofline(table, live, dtype_tag):
+    """Dominant kernel (largest total time in the profiling pass) and its
+    algorithmic bandwidth from the launches timed live in the timed region."""
+    tot = sum(r["ms"] for r in table)
+    avg_ms = live["ms"] / live["count"]
+    gbs = live["bytes"] / (avg_ms * 1e-3) / 1e9
+    kernels = {r["name"]: dict(launches=r["count"], total_ms=round(r["ms"], 3),
+                               avg_us=round(1e3 * r["ms"] / r["count"], 2),
+                               gbs=round(r["bytes"] / (r["ms"] / r["count"] * 1e-3) / 1e9, 1)
+                               if r["bytes"] > 0 else None,
+                               share=round(r["ms"] / tot, 4)) for r in table}
+    traffic, source = stored_traffic(live["name"], dtype_tag)
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else round(traffic),
+                kernel=live["name"], launches_timed=live["count"],
+                avg_us=round(1e3 * avg_ms, 2), bytes_per_launch=live["bytes"],
+                traffic_source=source), kernels
+
+
+def fft_compare(ctx):
+    """One 256^3 FP32 real FFT round trip through torch.fft (hipFFT/rocFFT)
+    and through this library's passes (median of 10 each, HIP events).
+    Comparison only: the hot path never calls a vendor FFT."""
+    import torch
+    n = ctx.n
+    x = torch.randn((n, n, n), dtype=torch.float32, device=ctx.device)
+
+    def med(fn):
+        ts = []
+        for i in range(13):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            if i >= 3:
+                ts.append(a.elapsed_time(b))
+        return sorted(ts)[len(ts) // 2]
+
+    vendor = med(lambda: torch.fft.irfftn(torch.fft.rfftn(x), s=(n, n, n)))
+    ours = med(lambda: ctx.irfft(ctx.rfft(x)))
+    return dict(n=n, dtype="f32", torch_fft_ms=round(vendor, 3), library_ms=round(ours, 3),
+                note="rfftn + irfftn round trip; the library figure includes its copies "
+                     "between the padded and the contiguous half-spectrum layouts")
 
 
 def cpu_baseline(cfg):
@@ -187,7 +258,11 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fft-compare", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, one device copy of this many MiB (a known-size "
+                         "kernel for calibrating hardware byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the hot path is single-GPU (multi-GPU sharding is "
@@ -207,13 +282,15 @@ def main():
 
     log("bench: building FP32 context for %s" % WORKLOAD[a.config])
     ctx, s, counts, s_start = setup(cfg, "f32")
-    log("bench: FP32 warmup %d + timed %d steps" % (a.warmup, a.steps))
-    r32 = timed_loop(ctx, s, a.steps, a.warmup, rom_every)
+    log("bench: FP32 warmup %d + profiling pass %d + timed %d steps"
+        % (a.warmup, a.profile_steps, a.steps))
+    r32 = timed_loop(ctx, s, a.steps, a.warmup, rom_every, max(1, a.profile_steps))
     log("bench: FP32 %d evals in %.3f s" % (r32["evals"], r32["seconds"]))
-    log("bench: per-kernel timing pass (%d steps)" % a.profile_steps)
-    rows = kernel_table(ctx, s, r32["g"], r32["loss"], a.warmup + a.steps, a.profile_steps,
-                        rom_every)
-    roof, table = roofline(rows)
+    roof, table = roofline(r32["table"], r32["live"], "fp32")
+    fftc = None
+    if not a.no_fft_compare:
+        log("bench: FFT round-trip comparison")
+        fftc = fft_compare(ctx)
     ws_gb = ctx.ws_bytes / 1e9
     del ctx, s
     r32.pop("g")
@@ -259,9 +336,16 @@ def main():
             "evaluations": r64["evals"], "ms_per_step": round(1e3 * r64["seconds"] / a.steps, 3)},
         "roofline": roof,
         "kernels": table,
+        "fft_compare": fftc,
         "workspace_gb": round(ws_gb, 2),
         "cpu_baseline": cpu,
     }
+    if a.copy_mib > 0:
+        src = torch.ones(a.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of %d MiB done" % a.copy_mib)
     print(json.dumps(out), flush=True)
 
 

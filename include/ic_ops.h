@@ -80,8 +80,16 @@ int ic_host_coefficients(const ic_problem* p, double* out, size_t n);
 
 /* Per-kernel timing with HIP events on the context stream: enable != 0
  * starts recording (resetting the totals), 0 stops.  ic_timing_report
- * writes "name count total_ms bytes_per_launch" lines into buf. */
+ * writes "name count total_ms bytes_per_launch" lines into buf, where
+ * bytes_per_launch counts each field a launch reads or writes once; while
+ * every kernel is recorded it also appends the tile-window statistics
+ * ("tiles_<kernel> windows 0 cells", "tiles_direct_<kernel> tiles 0 0",
+ * "tiles_max_<kernel> cells 0 0").  ic_timing_only starts recording the
+ * launches of one kernel name only (kernel: a name the report uses, not
+ * NULL), with no window statistics, so timed code is otherwise unchanged;
+ * ic_timing(ctx, 0) stops it. */
 int ic_timing(ic_ctx* ctx, int enable);
+int ic_timing_only(ic_ctx* ctx, const char* kernel);
 int ic_timing_report(ic_ctx* ctx, char* buf, size_t len);
 
 #ifdef __cplusplus

@@ -26,7 +26,7 @@ EXPORTS = [
     "ic_vjp", "ic_project_rankmatch", "ic_lbfgs_step", "ic_lbfgs_reset", "ic_op_rfft",
     "ic_op_irfft", "ic_op_multiplier", "ic_op_paint", "ic_op_force", "ic_op_lpt",
     "ic_op_evolve", "ic_op_sort_desc", "ic_op_philox", "ic_debug_rom_order", "ic_timing",
-    "ic_timing_report", "ic_host_coefficients",
+    "ic_timing_only", "ic_timing_report", "ic_host_coefficients",
 ]
 
 
@@ -99,6 +99,7 @@ _SIGS = {
     "ic_host_coefficients": (_I, [ctypes.POINTER(IcProblem), ctypes.POINTER(ctypes.c_double),
                                   ctypes.c_size_t]),
     "ic_timing": (_I, [_P, _I]),
+    "ic_timing_only": (_I, [_P, ctypes.c_char_p]),
     "ic_timing_report": (_I, [_P, ctypes.c_char_p, ctypes.c_size_t]),
 }
 

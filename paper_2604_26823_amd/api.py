@@ -264,6 +264,10 @@ class Context:
     def timing(self, enable):
         self._check(self.lib.ic_timing(self.ctx, 1 if enable else 0))
 
+    def timing_only(self, kernel):
+        """Record only the launches of one kernel (stop with timing(False))."""
+        self._check(self.lib.ic_timing_only(self.ctx, kernel.encode()))
+
     def timing_report(self):
         buf = ctypes.create_string_buffer(1 << 16)
         self._check(self.lib.ic_timing_report(self.ctx, buf, len(buf)))

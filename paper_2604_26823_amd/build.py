@@ -65,6 +65,23 @@ def build(jobs=None, verbose=False):
     return LIB
 
 
+def sources_digest():
+    """SHA-256 over the device and host sources (names and contents) and the
+    public headers: identifies the kernels a stored hardware-counter summary
+    was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    paths = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))]
+    paths += [os.path.join(inc, f) for f in sorted(os.listdir(inc))]
+    for p in paths:
+        if os.path.isfile(p):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)

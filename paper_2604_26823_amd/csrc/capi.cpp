@@ -304,6 +304,11 @@ int ic_timing(ic_ctx* ctx, int enable) {
   return guarded(ctx, [&](ic::EngineBase& e) { e.timing(enable != 0); });
 }
 
+int ic_timing_only(ic_ctx* ctx, const char* kernel) {
+  if (!kernel) return fail(ctx, IC_ERR_INVALID_ARG, "null kernel name");
+  return guarded(ctx, [&](ic::EngineBase& e) { e.timing_only(kernel); });
+}
+
 int ic_timing_report(ic_ctx* ctx, char* buf, size_t len) {
   if (!buf || len == 0) return fail(ctx, IC_ERR_INVALID_ARG, "null buffer");
   return guarded(ctx, [&](ic::EngineBase& e) {

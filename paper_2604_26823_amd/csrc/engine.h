@@ -37,6 +37,7 @@ struct EngineBase {
   virtual void debug_rom_order(int space, int32_t* idx, void* keys, int32_t* bins, int64_t cap,
                                int64_t* n) = 0;
   virtual void timing(bool enable) = 0;
+  virtual void timing_only(const char* kernel) = 0;
   virtual std::string timing_report() = 0;
 };
 

@@ -305,6 +305,10 @@ class Engine final : public EngineBase {
     }
     timer_.enable(enable);
   }
+  void timing_only(const char* kernel) override {
+    if (!kernel || !*kernel) throw ApiError(IC_ERR_INVALID_ARG, "kernel name required");
+    timer_.enable(true, kernel);
+  }
   std::string timing_report() override {
     std::string r = timer_.report();
     std::vector<unsigned long long> cnt(kStatPerKernel * kStatKernels);
@@ -340,6 +344,12 @@ class Engine final : public EngineBase {
     return t;
   }
 
+  // Algorithmic bytes of one half spectrum of side n (the row padding of the
+  // stored layout is not counted).
+  double half_spectrum_bytes(int n) const {
+    return (double)n * n * (n / 2 + 1) * 2 * sizeT();
+  }
+
   FftArgs<T> fa(int grid) const {
     FftArgs<T> f;
     f.n = grid ? nm_ : np_;
@@ -369,9 +379,9 @@ class Engine final : public EngineBase {
     return r;
   }
 
-  // Window-overflow counter of a tiled kernel (only while timing is on).
+  // Window statistics of a tiled kernel (only while every kernel is timed).
   unsigned long long* ovf(int k) const {
-    return timer_.enabled() ? tstat_ + kStatPerKernel * k : nullptr;
+    return timer_.all() ? tstat_ + kStatPerKernel * k : nullptr;
   }
 
   T* dslot(int n) const { return dtape_ + (long long)n * 3 * P_; }
@@ -433,7 +443,7 @@ class Engine final : public EngineBase {
   }
 
   void paint(const T* d, pk::Grid<T> g, T* rho, long long ncells) {
-    auto sc = timer_.scope("cic_paint", (3.0 * P_ + ncells) * sizeT());
+    auto sc = timer_.scope("cic_paint", (3.0 * P_ + 2.0 * ncells) * sizeT());
     pk::k_paint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(d, P_, lp_, tg_, g, rho,
                                                                    ovf(0));
     IC_LAUNCHED();
@@ -456,7 +466,7 @@ class Engine final : public EngineBase {
     auto f = fa(grid);
     const long long H = grid ? Hm_ : Hp_;
     const double U = (double)(grid ? M_ : P_) * sizeT();
-    const double Hb = (double)H * 2 * sizeT();
+    const double Hb = half_spectrum_bytes(f.n);
     cx<T>* S0 = pool_;
     cx<T>* So[kMaxMul];
     for (int j = 0; j < m; ++j) So[j] = pool_ + (j + 1) * H;
@@ -495,7 +505,7 @@ class Engine final : public EngineBase {
     auto f = fa(grid);
     const long long H = grid ? Hm_ : Hp_;
     const double U = (double)(grid ? M_ : P_) * sizeT();
-    const double Hb = (double)H * 2 * sizeT();
+    const double Hb = half_spectrum_bytes(f.n);
     const cx<T>* Si[kMaxMul];
     for (int j = 0; j < m; ++j) {
       cx<T>* Sj = pool_ + j * H;
@@ -573,7 +583,7 @@ class Engine final : public EngineBase {
     for (int n = 0; n < S_; ++n) {
       fill(rhom_, T(0), M_);
       {
-        auto sc = timer_.scope("pm_step", (12.0 * P_ + 4.0 * M_) * sizeT());
+        auto sc = timer_.scope("pm_step", (12.0 * P_ + 5.0 * M_) * sizeT());
         pk::k_pm_step_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
             dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
             dslot(n + 1), rhom_, P_, lp_, tg_, gmesh(), ovf(1));
@@ -582,7 +592,7 @@ class Engine final : public EngineBase {
       force_from_density(gslot(n + 1));
     }
     fill(rhod_, T(0), P_);
-    auto sc = timer_.scope("final_rsd_paint", (10.0 * P_ + 3.0 * M_) * sizeT());
+    auto sc = timer_.scope("final_rsd_paint", (11.0 * P_ + 3.0 * M_) * sizeT());
     pk::k_final_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
         dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), gmesh(), rsd(), gdata(),
         rhod_, P_, lp_, tg_, ovf(2));
@@ -626,7 +636,7 @@ class Engine final : public EngineBase {
       if (!tape_forces_) force_mesh(dslot(n), g);
       fill(gbar_, T(0), 3 * M_);
       {
-        auto sc = timer_.scope("cic_paint_vec", (6.0 * P_ + 3.0 * M_) * sizeT());
+        auto sc = timer_.scope("cic_paint_vec", (6.0 * P_ + 6.0 * M_) * sizeT());
         pk::k_paint_vec_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
             dslot(n), pbar_, coef, P_, lp_, tg_, gmesh(), gbar_, M_, ovf(4));
         IC_LAUNCHED();

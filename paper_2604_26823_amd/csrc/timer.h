@@ -26,14 +26,20 @@ class KernelTimer {
 
   void set_stream(hipStream_t s) { stream_ = s; }
   bool enabled() const { return on_; }
+  // True while every kernel is recorded (no single-kernel filter).
+  bool all() const { return on_ && only_.empty(); }
 
-  void enable(bool on) {
+  // Starts (resetting the records) or stops recording.  A non-empty only
+  // restricts recording to the kernels of that name, so the timed code runs
+  // with two events per such launch and nothing else added.
+  void enable(bool on, const std::string& only = std::string()) {
     on_ = on;
+    only_ = on ? only : std::string();
     if (on) used_ = 0, recs_used_ = 0;
   }
 
   Scope scope(const char* name, double bytes) {
-    if (!on_) return Scope();
+    if (!on_ || (!only_.empty() && only_ != name)) return Scope();
     if (recs_used_ == recs_.size()) {
       Rec r;
       IC_HIP(hipEventCreate(&r.start));
@@ -90,6 +96,7 @@ class KernelTimer {
     hipEvent_t start = nullptr, stop = nullptr;
   };
   bool on_ = false;
+  std::string only_;
   hipStream_t stream_ = nullptr;
   std::vector<Rec> recs_;
   size_t recs_used_ = 0, used_ = 0;
