@@ -1,0 +1,668 @@
+// Eulerian block ordering of the particles (gfx950).
+//
+// The grid is cut into 8^3-cell blocks.  Every particle belongs to the block
+// of its CIC base cell (the wrapped floor cell of its position), so all eight
+// corners of its stencil fall inside that block extended by one cell on the
+// upper side: a fixed 9^3-cell window.  After each drift the particles are
+// counting-sorted by block (per-block counts with wavefront-aggregated
+// atomics, an exclusive scan, a scatter of the state into block order), and
+// every paint and readout then runs over work items of at most 512 particles
+// of one block, with the block's window in LDS:
+//   * paints accumulate in FP64 LDS windows (ds_add_f64; the FP32 LDS atomic
+//     add of gfx950 runs at a small fraction of the FP64 rate) and flush each
+//     non-zero window cell with one global atomic;
+//   * gathers read their mesh fields from a window loaded with coalesced
+//     loads.
+// Unlike windows around Lagrangian patches, these windows cannot overflow,
+// however far particles have moved or however strongly they cluster: a dense
+// block simply yields more work items.
+//
+// The order inside a block follows the atomic ranks, so it can differ from
+// run to run; the results then differ only by FP64 summation order in the
+// LDS windows before the single rounding to the mesh type, and by the order
+// of the global atomics, which is unordered anyway.
+//
+// Slot a of a sorted state holds the particle with Lagrangian index ids[a];
+// dest[a] gives its slot in the next order, so cotangents move back from one
+// order to the previous one by a gather through dest.
+#pragma once
+
+#include "particles.h"
+
+namespace ic {
+namespace bk {
+
+using pk::Grid;
+using pk::Stencil;
+
+constexpr int kLB = 3;                 // log2 of the block side in cells
+constexpr int kB = 1 << kLB;           // block side
+constexpr int kW = kB + 1;             // window side
+constexpr int kWin = kW * kW * kW;     // window cells (729)
+constexpr int kThreads = 256;
+constexpr int kPer = 2;                // particles per thread
+constexpr int kChunk = kThreads * kPer;  // particles per work item
+
+// Blocks of one grid of side 2^lm (lm >= 3).
+struct Layout {
+  int lm;   // log2 of the grid side
+  int lnb;  // log2 of the blocks per side
+};
+
+inline Layout layout_for(int lm) { return Layout{lm, lm - kLB}; }
+inline unsigned block_count(const Layout& L) { return 1u << (3 * L.lnb); }
+// Upper bound of the work items of P particles: each non-empty block gives
+// ceil(count / kChunk) <= count / kChunk + 1 items.
+inline unsigned max_items(const Layout& L, long long P) {
+  return static_cast<unsigned>((P + kChunk - 1) / kChunk) + block_count(L);
+}
+
+// Up to six field pointers of one state array set.
+template <typename T>
+struct Ptrs {
+  const T* p[6];
+};
+template <typename T>
+struct MPtrs {
+  T* p[6];
+};
+
+// Block of the (wrapped) base cell of stencil s; wraps s.i0 in place.
+template <typename T>
+__device__ __forceinline__ unsigned block_of(Stencil<T>& s, const Layout& L) {
+  const int mask = (1 << L.lm) - 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s.i0[a] &= mask;
+  return (static_cast<unsigned>(s.i0[0] >> kLB) << (2 * L.lnb)) |
+         (static_cast<unsigned>(s.i0[1] >> kLB) << L.lnb) |
+         static_cast<unsigned>(s.i0[2] >> kLB);
+}
+
+// Origin (cell coordinates) of block b.
+__device__ __forceinline__ void block_origin(unsigned b, const Layout& L, int o[3]) {
+  const unsigned m = (1u << L.lnb) - 1;
+  o[0] = static_cast<int>(b >> (2 * L.lnb)) << kLB;
+  o[1] = static_cast<int>((b >> L.lnb) & m) << kLB;
+  o[2] = static_cast<int>(b & m) << kLB;
+}
+
+// Window index of unwrapped cell c relative to origin o (c - o in [0, 8]).
+__device__ __forceinline__ int win_index(const int o[3], int cx, int cy, int cz) {
+  return ((cx - o[0]) * kW + (cy - o[1])) * kW + (cz - o[2]);
+}
+
+// Mesh index of window cell k of the window at origin o.
+__device__ __forceinline__ unsigned win_cell(const int o[3], int k, const Layout& L) {
+  const unsigned mask = (1u << L.lm) - 1;
+  const int kx = k / (kW * kW), r = k - kx * kW * kW;
+  const int ky = r / kW, kz = r - ky * kW;
+  return ((static_cast<unsigned>(o[0] + kx) & mask) << (2 * L.lm)) |
+         ((static_cast<unsigned>(o[1] + ky) & mask) << L.lm) |
+         (static_cast<unsigned>(o[2] + kz) & mask);
+}
+
+// Rank of this lane's particle within its block: one atomic per distinct
+// key of the wavefront (the lanes sharing a key take consecutive ranks).
+// Every lane of the wavefront must call it; inactive lanes pass active =
+// false and get 0.
+__device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
+                                                  unsigned* __restrict__ count) {
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long todo = __ballot(active);
+  unsigned rank = 0;
+  while (todo) {
+    const int leader = __ffsll(static_cast<long long>(todo)) - 1;
+    const unsigned k = static_cast<unsigned>(__shfl(static_cast<int>(key), leader, 64));
+    const unsigned long long same = __ballot(active && key == k);
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(count + k, static_cast<unsigned>(__popcll(same)));
+    base = static_cast<unsigned>(__shfl(static_cast<int>(base), leader, 64));
+    if (active && key == k) rank = base + static_cast<unsigned>(__popcll(same & below));
+    todo &= ~same;
+  }
+  return rank;
+}
+
+// ---------------------------------------------------------------- sorting
+// Key and rank of every slot: the block of the stencil of displacement d
+// (particle ids[a], or a when ids is null) on grid g.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_keys(const T* __restrict__ d,
+                                                   const unsigned* __restrict__ ids, long long P,
+                                                   int lp, Grid<T> g, Layout L,
+                                                   unsigned* __restrict__ count,
+                                                   unsigned* __restrict__ key,
+                                                   unsigned* __restrict__ rank) {
+  const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
+  const bool ok = a < P;
+  unsigned b = 0;
+  if (ok) {
+    const long long j = ids ? static_cast<long long>(ids[a]) : a;
+    int idx[3];
+    pk::lattice(j, lp, idx);
+    T dsp[3];
+    pk::load3(d, P, a, dsp);
+    Stencil<T> s = pk::stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
+    b = block_of(s, L);
+  }
+  const unsigned r = rank_in_block(b, ok, count);
+  if (ok) {
+    key[a] = b;
+    rank[a] = r;
+  }
+}
+
+// Exclusive scan of the per-block counts and item counts
+// (ceil(count / kChunk)) in three phases: chunk sums, a one-workgroup scan
+// of the chunk sums, and the chunk-local scans with their offsets.  start and
+// istart get nb + 1 entries (the last = the totals).
+constexpr int kScanChunk = 2048;  // blocks per chunk (256 threads x 8)
+
+static __global__ __launch_bounds__(256) void k_scan_sums(const unsigned* __restrict__ count,
+                                                   unsigned nb, uint2* __restrict__ sums) {
+  __shared__ unsigned sc[256], si[256];
+  unsigned c = 0, it = 0;
+  const unsigned base = blockIdx.x * kScanChunk;
+  for (int j = 0; j < kScanChunk / 256; ++j) {
+    const unsigned i = base + j * 256 + threadIdx.x;
+    if (i < nb) {
+      const unsigned v = count[i];
+      c += v;
+      it += (v + kChunk - 1) / kChunk;
+    }
+  }
+  sc[threadIdx.x] = c;
+  si[threadIdx.x] = it;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sc[threadIdx.x] += sc[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = make_uint2(sc[0], si[0]);
+}
+
+// In-place exclusive scan of n <= 1024 pairs by one workgroup of 1024 threads.
+static __global__ __launch_bounds__(1024) void k_scan_top(uint2* __restrict__ sums, unsigned n) {
+  __shared__ unsigned a[1024], b[1024];
+  const unsigned t = threadIdx.x;
+  const uint2 v = t < n ? sums[t] : make_uint2(0u, 0u);
+  a[t] = v.x;
+  b[t] = v.y;
+  __syncthreads();
+  for (unsigned off = 1; off < 1024; off <<= 1) {
+    const unsigned xa = t >= off ? a[t - off] : 0u, xb = t >= off ? b[t - off] : 0u;
+    __syncthreads();
+    a[t] += xa;
+    b[t] += xb;
+    __syncthreads();
+  }
+  if (t < n) sums[t] = make_uint2(a[t] - v.x, b[t] - v.y);
+}
+
+static __global__ __launch_bounds__(256) void k_scan_out(const unsigned* __restrict__ count, unsigned nb,
+                                                  const uint2* __restrict__ sums,
+                                                  unsigned* __restrict__ start,
+                                                  unsigned* __restrict__ istart) {
+  __shared__ unsigned sc[256], si[256];
+  constexpr int kPerT = kScanChunk / 256;
+  const unsigned base = blockIdx.x * kScanChunk + threadIdx.x * kPerT;
+  unsigned c[kPerT], it[kPerT], tc = 0, ti = 0;
+#pragma unroll
+  for (int j = 0; j < kPerT; ++j) {
+    const unsigned i = base + j;
+    const unsigned v = i < nb ? count[i] : 0u;
+    c[j] = v;
+    it[j] = (v + kChunk - 1) / kChunk;
+    tc += c[j];
+    ti += it[j];
+  }
+  sc[threadIdx.x] = tc;
+  si[threadIdx.x] = ti;
+  __syncthreads();
+  for (unsigned off = 1; off < 256; off <<= 1) {
+    const unsigned xa = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+    const unsigned xb = threadIdx.x >= off ? si[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sc[threadIdx.x] += xa;
+    si[threadIdx.x] += xb;
+    __syncthreads();
+  }
+  unsigned oc = sums[blockIdx.x].x + sc[threadIdx.x] - tc;
+  unsigned oi = sums[blockIdx.x].y + si[threadIdx.x] - ti;
+#pragma unroll
+  for (int j = 0; j < kPerT; ++j) {
+    const unsigned i = base + j;
+    if (i < nb) {
+      start[i] = oc;
+      istart[i] = oi;
+    }
+    oc += c[j];
+    oi += it[j];
+    if (i + 1 == nb) {
+      start[nb] = oc;
+      istart[nb] = oi;
+    }
+  }
+}
+
+// Work items: item istart[b] + j = (block b, first slot start[b] + j kChunk).
+static __global__ __launch_bounds__(256) void k_fill_items(const unsigned* __restrict__ start,
+                                                    const unsigned* __restrict__ istart,
+                                                    unsigned nb, uint2* __restrict__ items) {
+  for (unsigned b = blockIdx.x * 256 + threadIdx.x; b < nb; b += gridDim.x * 256) {
+    const unsigned s0 = start[b], s1 = start[b + 1];
+    unsigned i = istart[b];
+    for (unsigned s = s0; s < s1; s += kChunk) items[i++] = make_uint2(b, s);
+  }
+}
+
+// Moves nf fields (and the ids) of slot a to slot start[key[a]] + rank[a] of
+// the new order; dest[a] receives that slot.  ids_src null means identity.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter(
+    const unsigned* __restrict__ key, const unsigned* __restrict__ rank,
+    const unsigned* __restrict__ start, Ptrs<T> src, MPtrs<T> dst, int nf,
+    const unsigned* __restrict__ ids_src, unsigned* __restrict__ ids_dst,
+    unsigned* __restrict__ dest, long long P) {
+  const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (a >= P) return;
+  const unsigned s = start[key[a]] + rank[a];
+  for (int f = 0; f < nf; ++f) dst.p[f][s] = src.p[f][a];
+  ids_dst[s] = ids_src ? ids_src[a] : static_cast<unsigned>(a);
+  dest[a] = s;
+}
+
+// dst_f[a] = src_f[dest[a]] for nf fields: values of the next order brought
+// back to this one.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather_back(const unsigned* __restrict__ dest,
+                                                          Ptrs<T> src, MPtrs<T> dst, int nf,
+                                                          long long P) {
+  const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (a >= P) return;
+  const unsigned s = dest[a];
+  for (int f = 0; f < nf; ++f) dst.p[f][a] = src.p[f][s];
+}
+
+// dst_f[ids[a]] = src_f[a]: a sorted state back to lattice order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_to_lattice(const unsigned* __restrict__ ids,
+                                                         Ptrs<T> src, MPtrs<T> dst, int nf,
+                                                         long long P) {
+  const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (a >= P) return;
+  const unsigned j = ids[a];
+  for (int f = 0; f < nf; ++f) dst.p[f][j] = src.p[f][a];
+}
+
+// ------------------------------------------------------------ work items
+struct Items {
+  const uint2* items;
+  const unsigned* start;   // nb + 1 entries
+  const unsigned* nitems;  // device pointer to the item total
+  const unsigned* ids;
+};
+
+// Block, origin and slot range of this workgroup's item; false (for the
+// whole workgroup) past the last item.
+struct Item {
+  unsigned b;
+  int o[3];
+  unsigned s0, s1;
+};
+
+__device__ __forceinline__ bool item_of(const Items& it, const Layout& L, Item& m) {
+  if (blockIdx.x >= *it.nitems) return false;
+  const uint2 v = it.items[blockIdx.x];
+  m.b = v.x;
+  m.s0 = v.y;
+  const unsigned e = it.start[v.x + 1];
+  m.s1 = (m.s0 + kChunk < e) ? m.s0 + kChunk : e;
+  block_origin(m.b, L, m.o);
+  return true;
+}
+
+// Slot k of this thread in the item: slot index, Lagrangian lattice index.
+__device__ __forceinline__ bool item_slot(const Item& m, const Items& it, int k, int lp,
+                                          long long& a, int idx[3]) {
+  a = static_cast<long long>(m.s0) + threadIdx.x + k * kThreads;
+  if (a >= m.s1) return false;
+  pk::lattice(static_cast<long long>(it.ids[a]), lp, idx);
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> wrapped_stencil(const int idx[3], const T dsp[3],
+                                                      const Grid<T>& g) {
+  Stencil<T> s = pk::stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
+  const int mask = (1 << g.lm) - 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s.i0[a] &= mask;
+  return s;
+}
+
+// Loads nf window fields (mesh fields src.p[f]) into lds[f * kWin + k].
+template <typename T>
+__device__ __forceinline__ void load_window(const int o[3], const Layout& L, const Ptrs<T>& src,
+                                            int nf, T* lds) {
+  constexpr int kIt = (kWin + kThreads - 1) / kThreads;
+  T v[kIt][4];
+#pragma unroll
+  for (int j = 0; j < kIt; ++j) {
+    const int k = min(static_cast<int>(threadIdx.x) + j * kThreads, kWin - 1);
+    const unsigned c = win_cell(o, k, L);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      if (f < nf) v[j][f] = src.p[f][c];
+  }
+#pragma unroll
+  for (int j = 0; j < kIt; ++j) {
+    const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+    if (k < kWin) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        if (f < nf) lds[f * kWin + k] = v[j][f];
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_window(double* acc, int nf) {
+  for (int k = threadIdx.x; k < nf * kWin; k += kThreads) acc[k] = 0.0;
+}
+
+// Adds the non-zero cells of nf FP64 windows into the mesh fields dst.p[f].
+template <typename T>
+__device__ __forceinline__ void flush_window(const int o[3], const Layout& L, const double* acc,
+                                             int nf, const MPtrs<T>& dst) {
+  constexpr int kIt = (kWin + kThreads - 1) / kThreads;
+#pragma unroll
+  for (int j = 0; j < kIt; ++j) {
+    const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+    if (k >= kWin) continue;
+    const unsigned c = win_cell(o, k, L);
+    for (int f = 0; f < nf; ++f) {
+      const T v = static_cast<T>(acc[f * kWin + k]);
+      if (v != T(0)) pk::atomic_add(dst.p[f] + c, v);
+    }
+  }
+}
+
+// rho(c) += sum_n W(q_n + d_n - c) over the items of one order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, long long P,
+                                                      int lp, Grid<T> g, Layout L, Items it,
+                                                      T* __restrict__ rho) {
+  __shared__ double acc[kWin];
+  Item m;
+  if (!item_of(it, L, m)) return;
+  zero_window(acc, 1);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    if (!item_slot(m, it, k, lp, a, idx)) continue;
+    T dsp[3];
+    pk::load3(d, P, a, dsp);
+    const Stencil<T> s = wrapped_stencil(idx, dsp, g);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
+    });
+  }
+  __syncthreads();
+  flush_window<T>(m.o, L, acc, 1, MPtrs<T>{{rho}});
+}
+
+// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ d,
+                                                          const T* __restrict__ v, T coef,
+                                                          long long P, int lp, Grid<T> g,
+                                                          Layout L, Items it, T* __restrict__ out,
+                                                          long long M) {
+  __shared__ double acc[3 * kWin];
+  Item m;
+  if (!item_of(it, L, m)) return;
+  zero_window(acc, 3);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    if (!item_slot(m, it, k, lp, a, idx)) continue;
+    T dsp[3], vv[3];
+    pk::load3(d, P, a, dsp);
+    pk::load3(v, P, a, vv);
+    const double v0 = static_cast<double>(coef * vv[0]), v1 = static_cast<double>(coef * vv[1]),
+                 v2 = static_cast<double>(coef * vv[2]);
+    const Stencil<T> s = wrapped_stencil(idx, dsp, g);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      const int c = win_index(m.o, cx, cy, cz);
+      const double wd = static_cast<double>(w);
+      atomicAdd(&acc[c], wd * v0);
+      atomicAdd(&acc[kWin + c], wd * v1);
+      atomicAdd(&acc[2 * kWin + c], wd * v2);
+    });
+  }
+  __syncthreads();
+  flush_window<T>(m.o, L, acc, 3, MPtrs<T>{{out, out + M, out + 2 * M}});
+}
+
+// Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
+// state goes to (dn, pn) in this order with its block key and rank on grid L.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_step_b(
+    const T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ g, long long M,
+    T kick, T drift, long long P, int lp, Grid<T> gr, Layout L, Items it, T* __restrict__ dn,
+    T* __restrict__ pn, unsigned* __restrict__ count, unsigned* __restrict__ key,
+    unsigned* __restrict__ rank) {
+  __shared__ T lds[3 * kWin];
+  Item m;
+  if (!item_of(it, L, m)) return;
+  load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    const bool ok = item_slot(m, it, k, lp, a, idx);
+    unsigned b = 0;
+    if (ok) {
+      T dsp[3], mom[3], F[3] = {0, 0, 0};
+      pk::load3(d, P, a, dsp);
+      pk::load3(p, P, a, mom);
+      const Stencil<T> s = wrapped_stencil(idx, dsp, gr);
+      pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+        const int c = win_index(m.o, cx, cy, cz);
+        F[0] += w * lds[c];
+        F[1] += w * lds[kWin + c];
+        F[2] += w * lds[2 * kWin + c];
+      });
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        mom[q] += kick * F[q];
+        pn[q * P + a] = mom[q];
+        dsp[q] += drift * mom[q];
+        dn[q * P + a] = dsp[q];
+      }
+      Stencil<T> s2 = pk::stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
+      b = block_of(s2, L);
+    }
+    const unsigned r = rank_in_block(b, ok, count);
+    if (ok) {
+      key[a] = b;
+      rank[a] = r;
+    }
+  }
+}
+
+// Position cotangent of one force evaluation (see pk::k_force_adjoint) with
+// g (three meshes) and rho_bar read from one four-field window.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
+    const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
+    const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
+    int lp, Grid<T> gm, Layout L, Items it) {
+  __shared__ T lds[4 * kWin];
+  Item m;
+  if (!item_of(it, L, m)) return;
+  long long a[kPer];
+  int idx[kPer][3];
+  bool ok[kPer];
+  T dsp[kPer][3], pb[kPer][3], db[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a[k], dsp[k]);
+    pk::load3(pbar, P, a[k], pb[k]);
+    pk::load3(dbar, P, a[k], db[k]);
+  }
+  load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M, rho_bar}}, 4, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!ok[k]) continue;
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], gm);
+    const T v0 = coef * pb[k][0], v1 = coef * pb[k][1], v2 = coef * pb[k][2];
+    T xb[3] = {0, 0, 0};
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T, T d0, T d1, T d2) {
+      const int c = win_index(m.o, cx, cy, cz);
+      const T h = v0 * lds[c] + v1 * lds[kWin + c] + v2 * lds[2 * kWin + c] + lds[3 * kWin + c];
+      xb[0] += d0 * h;
+      xb[1] += d1 * h;
+      xb[2] += d2 * h;
+    });
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      db[k][q] += xb[q] * gm.inv_cell;
+      dbar[q * P + a[k]] = db[k][q];
+      if (drift != T(0)) pbar[q * P + a[k]] = pb[k][q] + drift * db[k][q];
+    }
+  }
+}
+
+// Last kick (readout of g at d), p updated in place; then the key and rank
+// of the redshift-space position on the data grid (layout Ld).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_final_b(
+    const T* __restrict__ d, T* __restrict__ p, const T* __restrict__ g, long long M, T kick,
+    long long P, int lp, Grid<T> gm, Layout L, Items it, pk::Rsd<T> rsd, Grid<T> gd,
+    Layout Ld, unsigned* __restrict__ count, unsigned* __restrict__ key,
+    unsigned* __restrict__ rank) {
+  __shared__ T lds[3 * kWin];
+  Item m;
+  if (!item_of(it, L, m)) return;
+  load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    const bool ok = item_slot(m, it, k, lp, a, idx);
+    unsigned b = 0;
+    if (ok) {
+      T dsp[3], mom[3], F[3] = {0, 0, 0}, ds[3];
+      pk::load3(d, P, a, dsp);
+      pk::load3(p, P, a, mom);
+      const Stencil<T> s = wrapped_stencil(idx, dsp, gm);
+      pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+        const int c = win_index(m.o, cx, cy, cz);
+        F[0] += w * lds[c];
+        F[1] += w * lds[kWin + c];
+        F[2] += w * lds[2 * kWin + c];
+      });
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        mom[q] += kick * F[q];
+        p[q * P + a] = mom[q];
+      }
+      pk::rsd_shift(rsd, idx, dsp, mom, ds);
+      Stencil<T> s2 = pk::stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
+      b = block_of(s2, Ld);
+    }
+    const unsigned r = rank_in_block(b, ok, count);
+    if (ok) {
+      key[a] = b;
+      rank[a] = r;
+    }
+  }
+}
+
+// Data-grid paint of the redshift-space positions (items of the data order).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__ d,
+                                                           const T* __restrict__ p, long long P,
+                                                           int lp, pk::Rsd<T> rsd, Grid<T> gd,
+                                                           Layout Ld, Items it,
+                                                           T* __restrict__ rho) {
+  __shared__ double acc[kWin];
+  Item m;
+  if (!item_of(it, Ld, m)) return;
+  zero_window(acc, 1);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    if (!item_slot(m, it, k, lp, a, idx)) continue;
+    T dsp[3], mom[3], ds[3];
+    pk::load3(d, P, a, dsp);
+    pk::load3(p, P, a, mom);
+    pk::rsd_shift(rsd, idx, dsp, mom, ds);
+    const Stencil<T> s = wrapped_stencil(idx, ds, gd);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
+    });
+  }
+  __syncthreads();
+  flush_window<T>(m.o, Ld, acc, 1, MPtrs<T>{{rho}});
+}
+
+// Adjoint of the RSD + data paint (see pk::k_data_adjoint) over the data
+// order: d_bar, p_bar in that order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_data_adjoint_b(
+    const T* __restrict__ d, const T* __restrict__ p, long long P, int lp, pk::Rsd<T> rsd,
+    Grid<T> gd, Layout Ld, Items it, const T* __restrict__ rho_bar, T* __restrict__ dbar,
+    T* __restrict__ pbar) {
+  __shared__ T lds[kWin];
+  Item m;
+  if (!item_of(it, Ld, m)) return;
+  load_window<T>(m.o, Ld, Ptrs<T>{{rho_bar}}, 1, lds);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    long long a;
+    int idx[3];
+    if (!item_slot(m, it, k, lp, a, idx)) continue;
+    T dsp[3], mom[3], ds[3];
+    pk::load3(d, P, a, dsp);
+    pk::load3(p, P, a, mom);
+    pk::rsd_shift(rsd, idx, dsp, mom, ds);
+    const Stencil<T> s = wrapped_stencil(idx, ds, gd);
+    T xb[3] = {0, 0, 0};
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T, T d0, T d1, T d2) {
+      const T r = lds[win_index(m.o, cx, cy, cz)];
+      xb[0] += d0 * r;
+      xb[1] += d1 * r;
+      xb[2] += d2 * r;
+    });
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xb[q] *= gd.inv_cell;
+    T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
+    pk::rsd_transpose(rsd, idx, dsp, mom, xb, db, pb);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dbar[q * P + a] = db[q];
+      pbar[q * P + a] = pb[q];
+    }
+  }
+}
+
+}  // namespace bk
+}  // namespace ic

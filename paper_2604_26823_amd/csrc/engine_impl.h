@@ -15,8 +15,8 @@
 #include "engine.h"
 #include "fft.h"
 #include "fields.h"
+#include "blocks.h"
 #include "particles.h"
-#include "particles_tiled.h"
 #include "sort.h"
 #include "timer.h"
 
@@ -69,7 +69,12 @@ class Engine final : public EngineBase {
     Hm_ = (long long)nm_ * nm_ * kpm_;
     Hq_ = (long long)np_ * np_ * (np_ / 2 + 1);
     tape_forces_ = p.tape_forces != 0;
-    tg_ = tk::tile_geom(np_);
+    Lm_ = bk::layout_for(lm_);
+    Ld_ = bk::layout_for(lp_);
+    nbm_ = bk::block_count(Lm_);
+    nbd_ = bk::block_count(Ld_);
+    mim_ = bk::max_items(Lm_, P_);
+    mid_ = bk::max_items(Ld_, P_);
     const int m = std::max(1, p.lbfgs_m);
     wtab_len_ = 3 * (np_ / 2) * (np_ / 2) + 1;
     sort_blocks_ = (P_ + sk::kTile - 1) / sk::kTile;
@@ -108,7 +113,27 @@ class Engine final : public EngineBase {
     vbuf_ = c.take<T>(P_);
     tbuf_ = c.take<T>(P_);
     binc_ = c.take<uint32_t>(256);
-    tstat_ = c.take<unsigned long long>(kStatPerKernel * kStatKernels);
+    // Block orders of the particles: one per mesh state d_0..d_S, one on the
+    // data grid; ids and dest per order (see blocks.h).
+    idtape_ = c.take<uint32_t>((size_t)(S_ + 1) * P_);
+    desttape_ = c.take<uint32_t>((size_t)(S_ + 2) * P_);
+    ostart_ = c.take<uint32_t>((size_t)(S_ + 1) * (nbm_ + 1));
+    oistart_ = c.take<uint32_t>((size_t)(S_ + 1) * (nbm_ + 1));
+    oitems_ = c.take<uint2>((size_t)(S_ + 1) * mim_);
+    dstart_ = c.take<uint32_t>(nbd_ + 1);
+    distart_ = c.take<uint32_t>(nbd_ + 1);
+    ditems_ = c.take<uint2>(mid_);
+    dids_ = c.take<uint32_t>(P_);
+    bcount_ = c.take<uint32_t>(std::max(nbm_, nbd_));
+    bkey_ = c.take<uint32_t>(P_);
+    brank_ = c.take<uint32_t>(P_);
+    bsums_ = c.take<uint2>(1024);
+    tmpd_ = c.take<T>(3 * P_);
+    tmpp_ = c.take<T>(3 * P_);
+    dsd_ = c.take<T>(3 * P_);
+    psd_ = c.take<T>(3 * P_);
+    dbar2_ = c.take<T>(3 * P_);
+    pbar2_ = c.take<T>(3 * P_);
     dbg_idx_[0] = c.take<uint32_t>(P_);
     dbg_key_[0] = c.take<T>(P_);
     dbg_idx_[1] = c.take<uint32_t>(Hq_);
@@ -236,30 +261,30 @@ class Engine final : public EngineBase {
   }
 
   void op_paint(int grid, const void* disp, void* rho) override {
-    T* r = static_cast<T*>(rho);
-    const long long n3 = grid ? M_ : P_;
-    fill(r, T(0), n3);
-    paint(static_cast<const T*>(disp), grid ? gmesh() : gdata(), r, n3);
+    paint_lattice(static_cast<const T*>(disp), grid, static_cast<T*>(rho));
   }
 
   void op_force(const void* disp, void* force) override {
     const T* d = static_cast<const T*>(disp);
-    force_mesh(d, gtape_);
+    paint_lattice(d, 1, rhom_);
+    force_from_density(gtape_);
     pk::k_readout<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
         d, gtape_, M_, static_cast<T*>(force), P_, lp_, gmesh());
     IC_LAUNCHED();
   }
 
   void op_lpt(const void* s, void* d0, void* p0) override {
-    lpt(static_cast<const T*>(s));
-    copy(dtape_, static_cast<T*>(d0), 3 * P_);
-    copy(p_, static_cast<T*>(p0), 3 * P_);
+    lpt(static_cast<const T*>(s), static_cast<T*>(d0), static_cast<T*>(p0));
   }
 
+  // Final state in lattice order.
   void op_evolve(const void* s, void* d, void* p) override {
     run_forward(static_cast<const T*>(s));
-    copy(dslot(S_), static_cast<T*>(d), 3 * P_);
-    copy(p_, static_cast<T*>(p), 3 * P_);
+    T* dd = static_cast<T*>(d);
+    T* pp = static_cast<T*>(p);
+    bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+        ids(S_), state_ptrs(dslot(S_), p_), state_mptrs(dd, pp), 6, P_);
+    IC_LAUNCHED();
   }
 
   void op_sort_desc(const void* values, int64_t n, int32_t* order) override {
@@ -299,38 +324,12 @@ class Engine final : public EngineBase {
     IC_HIP(hipStreamSynchronize(st_));
   }
 
-  void timing(bool enable) override {
-    if (enable) {
-      ek_fill_u32(reinterpret_cast<uint32_t*>(tstat_), 0u, 2 * kStatPerKernel * kStatKernels);
-    }
-    timer_.enable(enable);
-  }
+  void timing(bool enable) override { timer_.enable(enable); }
   void timing_only(const char* kernel) override {
     if (!kernel || !*kernel) throw ApiError(IC_ERR_INVALID_ARG, "kernel name required");
     timer_.enable(true, kernel);
   }
-  std::string timing_report() override {
-    std::string r = timer_.report();
-    std::vector<unsigned long long> cnt(kStatPerKernel * kStatKernels);
-    IC_HIP(hipMemcpyAsync(cnt.data(), tstat_, cnt.size() * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, st_));
-    IC_HIP(hipStreamSynchronize(st_));
-    // Rows "tiles_<kernel> windows 0 cells", "tiles_direct_<kernel> tiles 0 0"
-    // and "tiles_max_<kernel> cells 0 0".
-    for (int k = 0; k < kStatKernels; ++k) {
-      unsigned long long v[4] = {0, 0, 0, 0};
-      for (int j = 0; j < tk::kStatSlots; ++j) {
-        const unsigned long long* s = cnt.data() + k * kStatPerKernel + tk::kStatWords * j;
-        for (int q = 0; q < 3; ++q) v[q] += s[q];
-        v[3] = std::max(v[3], s[3]);
-      }
-      const std::string nm = kStatNames[k];
-      r += "tiles_" + nm + " " + std::to_string(v[0]) + " 0 " + std::to_string(v[2]) + "\n";
-      r += "tiles_direct_" + nm + " " + std::to_string(v[1]) + " 0 0\n";
-      r += "tiles_max_" + nm + " " + std::to_string(v[3]) + " 0 0\n";
-    }
-    return r;
-  }
+  std::string timing_report() override { return timer_.report(); }
 
  private:
   // ------------------------------------------------------------- helpers
@@ -377,11 +376,6 @@ class Engine final : public EngineBase {
     r.dq = static_cast<T>(prob_.box / np_);
     for (int a = 0; a < 3; ++a) r.obs[a] = static_cast<T>(prob_.observer[a]);
     return r;
-  }
-
-  // Window statistics of a tiled kernel (only while every kernel is timed).
-  unsigned long long* ovf(int k) const {
-    return timer_.all() ? tstat_ + kStatPerKernel * k : nullptr;
   }
 
   T* dslot(int n) const { return dtape_ + (long long)n * 3 * P_; }
@@ -442,11 +436,84 @@ class Engine final : public EngineBase {
     IC_LAUNCHED();
   }
 
-  void paint(const T* d, pk::Grid<T> g, T* rho, long long ncells) {
-    auto sc = timer_.scope("cic_paint", (3.0 * P_ + 2.0 * ncells) * sizeT());
-    pk::k_paint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(d, P_, lp_, tg_, g, rho,
-                                                                   ovf(0));
+  // ------------------------------------------------------ block orders
+  struct Order {
+    unsigned* start;   // nb + 1
+    unsigned* istart;  // nb + 1 (istart[nb] = item count)
+    uint2* items;
+    unsigned nb;
+    unsigned max_items;
+  };
+  Order mesh_order(int n) const {
+    return Order{ostart_ + (size_t)n * (nbm_ + 1), oistart_ + (size_t)n * (nbm_ + 1),
+                 oitems_ + (size_t)n * mim_, nbm_, mim_};
+  }
+  Order data_order() const { return Order{dstart_, distart_, ditems_, nbd_, mid_}; }
+  unsigned* ids(int n) const { return idtape_ + (size_t)n * P_; }
+  // dest(n): slot in order n + 1 of each slot of order n (n = -1: lattice
+  // order to order 0); dest(S) maps order S to the data order.
+  unsigned* dest(int n) const { return desttape_ + (size_t)(n + 1) * P_; }
+  bk::Items items(const Order& o, const unsigned* id) const {
+    return bk::Items{o.items, o.start, o.istart + o.nb, id};
+  }
+
+  void zero_counts(unsigned nb) { ek_fill_u32(bcount_, 0u, nb); }
+
+  // Scan of the block counts in bcount_ into o, and its work items.
+  void build_order(const Order& o) {
+    auto sc = timer_.scope("sort_scan", 16.0 * o.nb);
+    const unsigned chunks = (o.nb + bk::kScanChunk - 1) / bk::kScanChunk;
+    if (chunks > 1024) throw ApiError(IC_ERR_UNSUPPORTED, "too many particle blocks");
+    bk::k_scan_sums<<<chunks, 256, 0, st_>>>(bcount_, o.nb, bsums_);
     IC_LAUNCHED();
+    bk::k_scan_top<<<1, 1024, 0, st_>>>(bsums_, chunks);
+    IC_LAUNCHED();
+    bk::k_scan_out<<<chunks, 256, 0, st_>>>(bcount_, o.nb, bsums_, o.start, o.istart);
+    IC_LAUNCHED();
+    bk::k_fill_items<<<grid_for(o.nb, 256), 256, 0, st_>>>(o.start, o.istart, o.nb, o.items);
+    IC_LAUNCHED();
+  }
+
+  // Moves nf state fields to the order o (keys and ranks in bkey_ / brank_).
+  void scatter(const Order& o, const bk::Ptrs<T>& src, const bk::MPtrs<T>& dst, int nf,
+               const unsigned* ids_src, unsigned* ids_dst, unsigned* dst_slots) {
+    auto sc = timer_.scope("sort_scatter", P_ * (2.0 * nf * sizeT() + 20.0));
+    bk::k_scatter<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+        bkey_, brank_, o.start, src, dst, nf, ids_src, ids_dst, dst_slots, P_);
+    IC_LAUNCHED();
+  }
+
+  // Keys and ranks of displacements d (lattice order) on grid g.
+  void keys_lattice(const T* d, const pk::Grid<T>& g, const bk::Layout& L, unsigned nb) {
+    zero_counts(nb);
+    auto sc = timer_.scope("sort_keys", P_ * (3.0 * sizeT() + 8.0));
+    bk::k_keys<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+        d, nullptr, P_, lp_, g, L, bcount_, bkey_, brank_);
+    IC_LAUNCHED();
+  }
+
+  // rho += CIC density of the state in order o (positions d, ids id).
+  void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
+             const bk::Layout& L, T* rho, long long ncells) {
+    auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
+    bk::k_paint_b<T><<<o.max_items, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L, items(o, id),
+                                                             rho);
+    IC_LAUNCHED();
+  }
+
+  // rho = CIC density of displacements d given in lattice order (sorted into
+  // the scratch order o first; tmpd_ receives the sorted positions).
+  void paint_lattice(const T* d, int grid, T* rho) {
+    const pk::Grid<T> g = grid ? gmesh() : gdata();
+    const bk::Layout& L = grid ? Lm_ : Ld_;
+    const Order o = grid ? mesh_order(0) : data_order();
+    const long long ncells = grid ? M_ : P_;
+    keys_lattice(d, g, L, o.nb);
+    build_order(o);
+    scatter(o, bk::Ptrs<T>{{d, d + P_, d + 2 * P_}},
+            bk::MPtrs<T>{{tmpd_, tmpd_ + P_, tmpd_ + 2 * P_}}, 3, nullptr, dids_, dest(-1));
+    fill(rho, T(0), ncells);
+    paint(tmpd_, o, dids_, g, L, rho, ncells);
   }
 
   // ------------------------------------------------------ k-space chains
@@ -532,15 +599,15 @@ class Engine final : public EngineBase {
   }
 
   // -------------------------------------------------------------- forward
-  // 2LPT from white noise: Psi1 -> dslot(0), Psi2 -> p_, then assembled.
-  void lpt(const T* s) {
+  // 2LPT from white noise in lattice order: Psi1 -> d0, Psi2 -> p0, then
+  // assembled into the displacement d0 and momentum p0 at a_init.
+  void lpt(const T* s, T* d0, T* p0) {
     const double inv = 1.0 / (double)P_;
     MulSpec sp[9] = {spec(MUL_WHITE | MUL_GRAD, 0, 0, inv), spec(MUL_WHITE | MUL_GRAD, 1, 0, inv),
                      spec(MUL_WHITE | MUL_GRAD, 2, 0, inv), spec(MUL_WHITE | MUL_HESS, 0, 0, inv),
                      spec(MUL_WHITE | MUL_HESS, 1, 1, inv), spec(MUL_WHITE | MUL_HESS, 2, 2, inv),
                      spec(MUL_WHITE | MUL_HESS, 0, 1, inv), spec(MUL_WHITE | MUL_HESS, 0, 2, inv),
                      spec(MUL_WHITE | MUL_HESS, 1, 2, inv)};
-    T* d0 = dslot(0);
     T* outs[9] = {d0, d0 + P_, d0 + 2 * P_, phi_, phi_ + P_, phi_ + 2 * P_,
                   phi_ + 3 * P_, phi_ + 4 * P_, phi_ + 5 * P_};
     chain_scatter(0, s, T(1), nullptr, T(0), outs, sp, 9);
@@ -551,12 +618,12 @@ class Engine final : public EngineBase {
     }
     MulSpec sp2[3] = {spec(MUL_GRAD, 0, 0, -inv), spec(MUL_GRAD, 1, 0, -inv),
                       spec(MUL_GRAD, 2, 0, -inv)};
-    T* outs2[3] = {p_, p_ + P_, p_ + 2 * P_};
+    T* outs2[3] = {p0, p0 + P_, p0 + 2 * P_};
     chain_scatter(0, mu_, T(1), nullptr, T(0), outs2, sp2, 3);
     const double a2E = prob_.a_init * prob_.a_init * co_.E_init;
     auto sc = timer_.scope("lpt_assemble", 12.0 * P_ * sizeT());
     fk::k_lpt_assemble<T><<<grid_for(3 * P_, kThreads), kThreads, 0, st_>>>(
-        d0, p_, static_cast<T>(co_.D1_init), static_cast<T>(co_.D2_init),
+        d0, p0, static_cast<T>(co_.D1_init), static_cast<T>(co_.D2_init),
         static_cast<T>(a2E * co_.f1_init * co_.D1_init),
         static_cast<T>(a2E * co_.f2_init * co_.D2_init), 3 * P_);
     IC_LAUNCHED();
@@ -571,32 +638,75 @@ class Engine final : public EngineBase {
     chain_scatter(1, rhom_, T(1), nullptr, T(0), outs, sp, 3);
   }
 
-  void force_mesh(const T* d, T* g) {
+  // Force meshes of the state d_n (order n).
+  void force_mesh(int n, T* g) {
     fill(rhom_, T(0), M_);
-    paint(d, gmesh(), rhom_, M_);
+    paint(dslot(n), mesh_order(n), ids(n), gmesh(), Lm_, rhom_, M_);
     force_from_density(g);
   }
 
+  // Forward model.  The 2LPT state is sorted into block order 0; every
+  // step reads the forces of its order, kicks and drifts, and sorts the new
+  // state into the next order (tapes: d_n, ids and dest per order); the last
+  // kick ends in order S, which the data paint re-sorts on the data grid.
   void run_forward(const T* s) {
-    lpt(s);
-    force_mesh(dslot(0), gslot(0));
+    lpt(s, tmpd_, tmpp_);
+    keys_lattice(tmpd_, gmesh(), Lm_, nbm_);
+    build_order(mesh_order(0));
+    scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), p_), 6, nullptr,
+            ids(0), dest(-1));
+    force_mesh(0, gslot(0));
     for (int n = 0; n < S_; ++n) {
-      fill(rhom_, T(0), M_);
+      zero_counts(nbm_);
       {
-        auto sc = timer_.scope("pm_step", (12.0 * P_ + 5.0 * M_) * sizeT());
-        pk::k_pm_step_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
+        auto sc = timer_.scope("pm_step", P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+        bk::k_step_b<T><<<mim_, bk::kThreads, 0, st_>>>(
             dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
-            dslot(n + 1), rhom_, P_, lp_, tg_, gmesh(), ovf(1));
+            P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_, bcount_, bkey_,
+            brank_);
         IC_LAUNCHED();
       }
-      force_from_density(gslot(n + 1));
+      build_order(mesh_order(n + 1));
+      scatter(mesh_order(n + 1), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(n + 1), p_), 6,
+              ids(n), ids(n + 1), dest(n));
+      force_mesh(n + 1, gslot(n + 1));
     }
+    zero_counts(nbd_);
+    {
+      auto sc = timer_.scope("final_kick", P_ * (9.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+      bk::k_final_b<T><<<mim_, bk::kThreads, 0, st_>>>(
+          dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_, gmesh(), Lm_,
+          items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
+      IC_LAUNCHED();
+    }
+    build_order(data_order());
+    scatter(data_order(), state_ptrs(dslot(S_), p_), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
+            dest(S_));
     fill(rhod_, T(0), P_);
-    auto sc = timer_.scope("final_rsd_paint", (11.0 * P_ + 3.0 * M_) * sizeT());
-    pk::k_final_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-        dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), gmesh(), rsd(), gdata(),
-        rhod_, P_, lp_, tg_, ovf(2));
+    auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0));
+    bk::k_data_paint_b<T><<<mid_, bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
+                                                           Ld_, items(data_order(), dids_), rhod_);
     IC_LAUNCHED();
+  }
+
+  bk::Ptrs<T> state_ptrs(const T* d, const T* p) const {
+    return bk::Ptrs<T>{{d, d + P_, d + 2 * P_, p, p + P_, p + 2 * P_}};
+  }
+  bk::MPtrs<T> state_mptrs(T* d, T* p) const {
+    return bk::MPtrs<T>{{d, d + P_, d + 2 * P_, p, p + P_, p + 2 * P_}};
+  }
+
+  // Cotangents (dbar_, pbar_) of one order brought back to the previous one
+  // through dest_slots (buffers swapped with dbar2_, pbar2_).
+  void cotangents_back(const unsigned* dest_slots) {
+    {
+      auto sc = timer_.scope("sort_gather_back", P_ * (12.0 * sizeT() + 4.0));
+      bk::k_gather_back<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+          dest_slots, state_ptrs(dbar_, pbar_), state_mptrs(dbar2_, pbar2_), 6, P_);
+      IC_LAUNCHED();
+    }
+    std::swap(dbar_, dbar2_);
+    std::swap(pbar_, pbar2_);
   }
 
   // Loss terms (and adjoint seed) from the data-grid density of the last forward.
@@ -623,22 +733,27 @@ class Engine final : public EngineBase {
   // Reverse sweep from the seed in seed_; out = J^T seed + beta_aux aux.
   void adjoint(T* out, const T* aux, T beta_aux) {
     {
-      auto sc = timer_.scope("data_adjoint", 13.0 * P_ * sizeT());
-      pk::k_data_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-          dslot(S_), p_, rsd(), gdata(), seed_, dbar_, pbar_, P_, lp_, tg_, ovf(3));
+      auto sc = timer_.scope("data_adjoint", P_ * (13.0 * sizeT() + 4.0));
+      bk::k_data_adjoint_b<T><<<mid_, bk::kThreads, 0, st_>>>(
+          dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), seed_, dbar2_,
+          pbar2_);
       IC_LAUNCHED();
     }
+    std::swap(dbar_, dbar2_);
+    std::swap(pbar_, pbar2_);
+    cotangents_back(dest(S_));
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
     const double sc_rho = -1.0 / ((double)P_ / (double)M_ * (double)M_);
     for (int n = S_; n >= 0; --n) {
       const T coef = static_cast<T>(co_.kick[n]);
       T* g = gslot(n);
-      if (!tape_forces_) force_mesh(dslot(n), g);
+      if (!tape_forces_) force_mesh(n, g);
+      const bk::Items it = items(mesh_order(n), ids(n));
       fill(gbar_, T(0), 3 * M_);
       {
-        auto sc = timer_.scope("cic_paint_vec", (6.0 * P_ + 6.0 * M_) * sizeT());
-        pk::k_paint_vec_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, tg_, gmesh(), gbar_, M_, ovf(4));
+        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 4.0) + 6.0 * M_ * sizeT());
+        bk::k_paint_vec_b<T><<<mim_, bk::kThreads, 0, st_>>>(dslot(n), pbar_, coef, P_, lp_,
+                                                             gmesh(), Lm_, it, gbar_, M_);
         IC_LAUNCHED();
       }
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
@@ -648,10 +763,14 @@ class Engine final : public EngineBase {
                        spec(MUL_GRAD, 2, 0, sc_rho)};
       chain_gather(1, ins, sp, 3, rhobar_, nullptr, T(0));
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
-      auto sc = timer_.scope("force_adjoint", (15.0 * P_ + 4.0 * M_) * sizeT());
-      pk::k_force_adjoint_t<T><<<tk::tile_count(tg_), tk::kThreads, 0, st_>>>(
-          dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, tg_, gmesh(), ovf(5));
-      IC_LAUNCHED();
+      {
+        auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 4.0) + 4.0 * M_ * sizeT());
+        bk::k_force_adjoint_b<T><<<mim_, bk::kThreads, 0, st_>>>(
+            dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it);
+        IC_LAUNCHED();
+      }
+      // To order n - 1 (the lattice order after n = 0).
+      cotangents_back(dest(n - 1));
     }
     // 2LPT and whitening adjoint.
     const double inv = 1.0 / (double)P_;
@@ -741,7 +860,6 @@ class Engine final : public EngineBase {
   long long Hp_, Hm_;      // stored half-spectrum sizes (padded rows)
   long long Hq_;           // half-spectrum modes of the particle grid, n^2 (n/2+1)
   bool tape_forces_;
-  tk::TileGeom tg_;
   int wtab_len_;
   long long sort_blocks_;
   size_t need_ = 0;
@@ -756,11 +874,12 @@ class Engine final : public EngineBase {
   T *hist_S_, *hist_Y_, *dir_, *strial_, *gtrial_;
   uint64_t *keys_, *keys2_;
   uint32_t *vals_, *vals2_, *small_, *shist_, *binc_;
-  unsigned long long* tstat_;  // per tiled kernel: tk::kStatSlots groups of 4 counters
-  static constexpr int kStatKernels = 6;
-  static constexpr int kStatPerKernel = tk::kStatWords * tk::kStatSlots;
-  static constexpr const char* kStatNames[kStatKernels] = {
-      "paint", "pm_step", "final", "data_adjoint", "paint_vec", "force_adjoint"};
+  bk::Layout Lm_{}, Ld_{};  // 8^3-cell blocks of the mesh and of the data grid
+  unsigned nbm_ = 0, nbd_ = 0, mim_ = 0, mid_ = 0;
+  uint32_t *idtape_, *desttape_, *ostart_, *oistart_, *dstart_, *distart_, *dids_;
+  uint2 *oitems_, *ditems_, *bsums_;
+  uint32_t *bcount_, *bkey_, *brank_;
+  T *tmpd_, *tmpp_, *dsd_, *psd_, *dbar2_, *pbar2_;
   T *vbuf_, *tbuf_;
   uint32_t* dbg_idx_[2];
   T* dbg_key_[2];

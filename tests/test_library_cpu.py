@@ -58,7 +58,9 @@ def test_workspace_sizes_and_validation(lib):
     rc, b32 = _size(lib, inputs.config(3))
     assert rc == 0
     rc, b64 = _size(lib, inputs.config(3), _lib.IC_F64)
-    assert rc == 0 and 1.9 < b64 / b32 < 2.1
+    # field buffers double; the 32-bit particle orders (ids, destinations,
+    # block keys) do not
+    assert rc == 0 and 1.6 < b64 / b32 < 2.1
     # 256^3 FP32 fits comfortably in one MI355X's 288 GB
     assert 4e9 < b32 < 2e10
     for bad in [dict(n_part=48), dict(n_part=1024, n_mesh=1024), dict(n_mesh=96)]:
