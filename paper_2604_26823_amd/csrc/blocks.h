@@ -101,27 +101,35 @@ __device__ __forceinline__ unsigned win_cell(const int o[3], int k, const Layout
          (static_cast<unsigned>(o[2] + kz) & mask);
 }
 
-// Rank of this lane's particle within its block: one atomic per distinct
-// key of the wavefront (the lanes sharing a key take consecutive ranks).
-// Every lane of the wavefront must call it; inactive lanes pass active =
-// false and get 0.
+// Rank of this lane's particle within its block.  The lanes of the
+// wavefront are grouped by key with ballots first; then each group's first
+// lane adds the group size to the block count, all groups in the same
+// atomic instruction, so the wavefront waits for one atomic round trip
+// whatever the number of distinct keys.  The lanes of a group take
+// consecutive ranks.  Every lane of the wavefront must call it; inactive
+// lanes pass active = false and get 0.
 __device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
                                                   unsigned* __restrict__ count) {
   const int lane = static_cast<int>(threadIdx.x & 63);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   unsigned long long todo = __ballot(active);
-  unsigned rank = 0;
+  int my_leader = 0;
+  unsigned my_off = 0, group = 0;
   while (todo) {
     const int leader = __ffsll(static_cast<long long>(todo)) - 1;
     const unsigned k = static_cast<unsigned>(__shfl(static_cast<int>(key), leader, 64));
     const unsigned long long same = __ballot(active && key == k);
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(count + k, static_cast<unsigned>(__popcll(same)));
-    base = static_cast<unsigned>(__shfl(static_cast<int>(base), leader, 64));
-    if (active && key == k) rank = base + static_cast<unsigned>(__popcll(same & below));
+    if (lane == leader) group = static_cast<unsigned>(__popcll(same));
+    if (active && key == k) {
+      my_leader = leader;
+      my_off = static_cast<unsigned>(__popcll(same & below));
+    }
     todo &= ~same;
   }
-  return rank;
+  unsigned base = 0;
+  if (group) base = atomicAdd(count + key, group);
+  base = static_cast<unsigned>(__shfl(static_cast<int>(base), my_leader, 64));
+  return active ? base + my_off : 0u;
 }
 
 // ---------------------------------------------------------------- sorting
