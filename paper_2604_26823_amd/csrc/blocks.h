@@ -56,6 +56,9 @@ inline unsigned block_count(const Layout& L) { return 1u << (3 * L.lnb); }
 inline unsigned max_items(const Layout& L, long long P) {
   return static_cast<unsigned>((P + kChunk - 1) / kChunk) + block_count(L);
 }
+// Workgroups of an item kernel: the item bound plus the slack of the XCD
+// dealing (item_of).
+inline unsigned item_grid(const Layout& L, long long P) { return max_items(L, P) + 8; }
 
 // Up to six field pointers of one state array set.
 template <typename T>
@@ -316,16 +319,34 @@ struct Items {
 };
 
 // Block, origin and slot range of this workgroup's item; false (for the
-// whole workgroup) past the last item.
+// whole workgroup) past the last item.  Workgroups are dealt to the eight
+// XCDs round-robin (workgroup w runs on XCD w mod 8).  Gathers (CONTIG) take
+// item (w mod 8) per + w / 8 with per = ceil(items / 8), so each XCD walks
+// one contiguous range of neighbouring blocks whose windows share cache
+// lines in that XCD's L2; paints take item w, so neighbouring blocks, whose
+// flushes add into the same halo cells, run on different XCDs and their
+// atomics do not queue behind each other.  The grid must hold at least
+// items + 7 workgroups.
+constexpr int kXcds = 8;
+
 struct Item {
   unsigned b;
   int o[3];
   unsigned s0, s1;
 };
 
+template <bool CONTIG>
 __device__ __forceinline__ bool item_of(const Items& it, const Layout& L, Item& m) {
-  if (blockIdx.x >= *it.nitems) return false;
-  const uint2 v = it.items[blockIdx.x];
+  const unsigned n = *it.nitems;
+  const unsigned w = blockIdx.x;
+  unsigned i = w;
+  if (CONTIG) {
+    const unsigned per = (n + kXcds - 1) / kXcds;
+    i = (w % kXcds) * per + w / kXcds;
+    if (w / kXcds >= per) return false;
+  }
+  if (i >= n) return false;
+  const uint2 v = it.items[i];
   m.b = v.x;
   m.s0 = v.y;
   const unsigned e = it.start[v.x + 1];
@@ -406,7 +427,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
                                                       T* __restrict__ rho) {
   __shared__ double acc[kWin];
   Item m;
-  if (!item_of(it, L, m)) return;
+  if (!item_of<false>(it, L, m)) return;
   zero_window(acc, 1);
   __syncthreads();
 #pragma unroll
@@ -434,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
                                                           long long M) {
   __shared__ double acc[3 * kWin];
   Item m;
-  if (!item_of(it, L, m)) return;
+  if (!item_of<false>(it, L, m)) return;
   zero_window(acc, 3);
   __syncthreads();
 #pragma unroll
@@ -470,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
     unsigned* __restrict__ rank) {
   __shared__ T lds[3 * kWin];
   Item m;
-  if (!item_of(it, L, m)) return;
+  if (!item_of<true>(it, L, m)) return;
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();
 #pragma unroll
@@ -517,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
     int lp, Grid<T> gm, Layout L, Items it) {
   __shared__ T lds[4 * kWin];
   Item m;
-  if (!item_of(it, L, m)) return;
+  if (!item_of<true>(it, L, m)) return;
   long long a[kPer];
   int idx[kPer][3];
   bool ok[kPer];
@@ -564,7 +585,7 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
     unsigned* __restrict__ rank) {
   __shared__ T lds[3 * kWin];
   Item m;
-  if (!item_of(it, L, m)) return;
+  if (!item_of<true>(it, L, m)) return;
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();
 #pragma unroll
@@ -610,7 +631,7 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
                                                            T* __restrict__ rho) {
   __shared__ double acc[kWin];
   Item m;
-  if (!item_of(it, Ld, m)) return;
+  if (!item_of<false>(it, Ld, m)) return;
   zero_window(acc, 1);
   __syncthreads();
 #pragma unroll
@@ -640,7 +661,7 @@ __global__ __launch_bounds__(kThreads) void k_data_adjoint_b(
     T* __restrict__ pbar) {
   __shared__ T lds[kWin];
   Item m;
-  if (!item_of(it, Ld, m)) return;
+  if (!item_of<true>(it, Ld, m)) return;
   load_window<T>(m.o, Ld, Ptrs<T>{{rho_bar}}, 1, lds);
   __syncthreads();
 #pragma unroll

@@ -496,7 +496,7 @@ class Engine final : public EngineBase {
   void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
              const bk::Layout& L, T* rho, long long ncells) {
     auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
-    bk::k_paint_b<T><<<o.max_items, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L, items(o, id),
+    bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L, items(o, id),
                                                              rho);
     IC_LAUNCHED();
   }
@@ -660,7 +660,7 @@ class Engine final : public EngineBase {
       zero_counts(nbm_);
       {
         auto sc = timer_.scope("pm_step", P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
-        bk::k_step_b<T><<<mim_, bk::kThreads, 0, st_>>>(
+        bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
             dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
             P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_, bcount_, bkey_,
             brank_);
@@ -674,7 +674,7 @@ class Engine final : public EngineBase {
     zero_counts(nbd_);
     {
       auto sc = timer_.scope("final_kick", P_ * (9.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
-      bk::k_final_b<T><<<mim_, bk::kThreads, 0, st_>>>(
+      bk::k_final_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
           dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_, gmesh(), Lm_,
           items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
       IC_LAUNCHED();
@@ -684,7 +684,7 @@ class Engine final : public EngineBase {
             dest(S_));
     fill(rhod_, T(0), P_);
     auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0));
-    bk::k_data_paint_b<T><<<mid_, bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
+    bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
                                                            Ld_, items(data_order(), dids_), rhod_);
     IC_LAUNCHED();
   }
@@ -734,7 +734,7 @@ class Engine final : public EngineBase {
   void adjoint(T* out, const T* aux, T beta_aux) {
     {
       auto sc = timer_.scope("data_adjoint", P_ * (13.0 * sizeT() + 4.0));
-      bk::k_data_adjoint_b<T><<<mid_, bk::kThreads, 0, st_>>>(
+      bk::k_data_adjoint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
           dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), seed_, dbar2_,
           pbar2_);
       IC_LAUNCHED();
@@ -752,7 +752,7 @@ class Engine final : public EngineBase {
       fill(gbar_, T(0), 3 * M_);
       {
         auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 4.0) + 6.0 * M_ * sizeT());
-        bk::k_paint_vec_b<T><<<mim_, bk::kThreads, 0, st_>>>(dslot(n), pbar_, coef, P_, lp_,
+        bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(dslot(n), pbar_, coef, P_, lp_,
                                                              gmesh(), Lm_, it, gbar_, M_);
         IC_LAUNCHED();
       }
@@ -765,7 +765,7 @@ class Engine final : public EngineBase {
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       {
         auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 4.0) + 4.0 * M_ * sizeT());
-        bk::k_force_adjoint_b<T><<<mim_, bk::kThreads, 0, st_>>>(
+        bk::k_force_adjoint_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
             dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it);
         IC_LAUNCHED();
       }
