@@ -169,8 +169,13 @@ template <typename T, int N> struct ZCfg {
   static constexpr int LINES0 = 256 / TPL;
   static constexpr int LINES = LINES0 > 64 ? 64 : (LINES0 < 1 ? 1 : LINES0);
   static constexpr int THREADS = LINES * TPL;
-  static constexpr int LS = n + 2;  // padded LDS line stride (complex)
+  // LDS line stride (complex): one pad element per 16 (zl) plus two, so
+  // the stride-16 accesses of the radix-16 stage fall in different banks.
+  static constexpr int LS = n + n / 16 + 2;
 };
+
+// Padded LDS position of element e of a z line.
+__device__ __forceinline__ int zl(int e) { return e + (e >> 4); }
 
 template <typename T, int N> struct SCfg {  // strided C2C passes
   static constexpr int TPL = Plan<N>::TPL;
@@ -222,16 +227,16 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
     return v;
   };
   cx<T>* lb = buf + l * C::LS;
-  auto lidx = [&](int e) { return l * C::LS + e; };
-  auto storeL = [&](int e, cx<T> v) { lb[e] = v; };
+  auto lidx = [&](int e) { return l * C::LS + zl(e); };
+  auto storeL = [&](int e, cx<T> v) { lb[zl(e)] = v; };
   fft_line<T, n, true>(lane, buf, lidx, tw, 2, load0, storeL);
   __syncthreads();
   if (!valid) return;
   cx<T>* o = out + (size_t)line * kp;
   const T half = static_cast<T>(0.5);
   for (int k = lane; k <= n; k += C::TPL) {
-    cx<T> zk = lb[k == n ? 0 : k];
-    cx<T> zc = cconj<T>(lb[k == 0 ? 0 : n - k]);
+    cx<T> zk = lb[zl(k == n ? 0 : k)];
+    cx<T> zc = cconj<T>(lb[zl(k == 0 ? 0 : n - k)]);
     cx<T> e = cscale<T>(cadd<T>(zk, zc), half);
     cx<T> d = cscale<T>(csub<T>(zk, zc), half);
     // X[k] = E + W^k (-i D), W = exp(-2 pi i / N)
@@ -259,19 +264,19 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
   for (int k = lane; k <= n; k += C::TPL) {
     cx<T> v = valid ? src[k] : mkc<T>(0, 0);
     if (k == 0 || k == n) v.y = 0;  // the real transform ignores these imaginary parts
-    lb[k] = v;
+    lb[zl(k)] = v;
   }
   __syncthreads();
   auto load0 = [&](int e) -> cx<T> {
-    cx<T> xk = lb[e];
-    cx<T> xc = cconj<T>(lb[n - e]);
+    cx<T> xk = lb[zl(e)];
+    cx<T> xc = cconj<T>(lb[zl(n - e)]);
     cx<T> s = cadd<T>(xk, xc);
     cx<T> d = csub<T>(xk, xc);
     cx<T> w = cconj<T>(tw[e]);  // exp(+2 pi i e / N)
     cx<T> wd = cmul<T>(w, d);
     return mkc<T>(s.x - wd.y, s.y + wd.x);  // s + i w d
   };
-  auto lidx = [&](int e) { return l * C::LS + e; };
+  auto lidx = [&](int e) { return l * C::LS + zl(e); };
   cx<T>* dst = reinterpret_cast<cx<T>*>(out + (size_t)line * N);
   const cx<T>* ax = aux ? reinterpret_cast<const cx<T>*>(aux + (size_t)line * N) : nullptr;
   auto storeL = [&](int e, cx<T> v) {
