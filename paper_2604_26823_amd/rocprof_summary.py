@@ -26,12 +26,16 @@ if os.path.dirname(HERE) not in sys.path:
 
 # Device kernel -> the name the library's timing report uses for it.
 SCOPES = {
-    "k_paint_vec_t": "cic_paint_vec",
-    "k_pm_step_t": "pm_step",
-    "k_force_adjoint_t": "force_adjoint",
-    "k_final_t": "final_rsd_paint",
-    "k_data_adjoint_t": "data_adjoint",
-    "k_paint_t": "cic_paint",
+    "k_paint_vec_b": "cic_paint_vec",
+    "k_step_b": "pm_step",
+    "k_force_adjoint_b": "force_adjoint",
+    "k_final_b": "final_kick",
+    "k_data_paint_b": "data_paint",
+    "k_data_adjoint_b": "data_adjoint",
+    "k_paint_b": "cic_paint",
+    "k_scatter": "sort_scatter",
+    "k_gather_back": "sort_gather_back",
+    "k_keys": "sort_keys",
     "k_r2c_z": "fft_r2c_z",
     "k_c2r_z": "fft_c2r_z",
     "k_strided": "fft_y",
