@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IC_ABI_VERSION 1
+#define IC_ABI_VERSION 2
 
 #define IC_OK 0
 #define IC_ERR_INVALID_ARG (-1)
@@ -98,6 +98,9 @@ typedef struct ic_problem {
   double s_th;           /* projection reset threshold (10) */
   int32_t rom_nbins;     /* Fourier-space matching bins (100) */
   int32_t tape_forces;   /* 1: keep force meshes for the adjoint; 0: recompute */
+  int32_t ckpt_every;    /* K > 0: keep particle states only at steps 0, K, 2K, ...
+                            and recompute the steps in between during the adjoint;
+                            0: keep every step's state */
   double rom_kmin;       /* smallest matched |k| (0.1 h/Mpc) */
   uint64_t seed;         /* key of the counter-based generator */
 } ic_problem;

@@ -42,6 +42,7 @@ class IcProblem(ctypes.Structure):
         ("max_trials", ctypes.c_int32), ("eps_max", ctypes.c_double),
         ("armijo_c1", ctypes.c_double), ("s_th", ctypes.c_double),
         ("rom_nbins", ctypes.c_int32), ("tape_forces", ctypes.c_int32),
+        ("ckpt_every", ctypes.c_int32),
         ("rom_kmin", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 

@@ -482,7 +482,8 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
 }
 
 // Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
-// state goes to (dn, pn) in this order with its block key and rank on grid L.
+// state goes to (dn, pn) in this order with its block key and rank on grid L
+// (no keys when count is null: a replay into an order already recorded).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_step_b(
     const T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ g, long long M,
@@ -521,6 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
       Stencil<T> s2 = pk::stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
       b = block_of(s2, L);
     }
+    if (!count) continue;
     const unsigned r = rank_in_block(b, ok, count);
     if (ok) {
       key[a] = b;

@@ -71,6 +71,7 @@ void validate_problem(const ic_problem& p) {
   if (!(p.eps_max > 0)) bad(IC_ERR_INVALID_ARG, "eps_max must be positive");
   if (!(p.s_th > 0)) bad(IC_ERR_INVALID_ARG, "s_th must be positive");
   if (p.rom_nbins < 1 || p.rom_nbins > 127) bad(IC_ERR_INVALID_ARG, "rom_nbins must be in [1, 127]");
+  if (p.ckpt_every < 0) bad(IC_ERR_INVALID_ARG, "ckpt_every must be >= 0");
 }
 
 size_t workspace_bytes(const ic_problem& p, int precision) {
@@ -117,6 +118,7 @@ void ic_problem_defaults(ic_problem* p) {
   p->s_th = IC_DEFAULT_S_TH;
   p->rom_nbins = IC_DEFAULT_ROM_NBINS;
   p->tape_forces = 1;
+  p->ckpt_every = 0;
   p->rom_kmin = IC_DEFAULT_ROM_KMIN;
   p->seed = 0;
 }

@@ -69,6 +69,8 @@ class Engine final : public EngineBase {
     Hm_ = (long long)nm_ * nm_ * kpm_;
     Hq_ = (long long)np_ * np_ * (np_ / 2 + 1);
     tape_forces_ = p.tape_forces != 0;
+    // Checkpoint spacing; a spacing beyond the last step keeps state 0 only.
+    K_ = p.ckpt_every > 0 ? std::min(p.ckpt_every, S_ + 1) : 0;
     Lm_ = bk::layout_for(lm_);
     Ld_ = bk::layout_for(lp_);
     nbm_ = bk::block_count(Lm_);
@@ -87,8 +89,13 @@ class Engine final : public EngineBase {
     pool_ = c.take<cx<T>>(pool_len_);
     phi_ = c.take<T>(6 * P_);
     mu_ = c.take<T>(P_);
-    dtape_ = c.take<T>((S_ + 1) * 3 * P_);
-    gtape_ = c.take<T>((tape_forces_ ? (S_ + 1) : 1) * 3 * M_);
+    // Particle states: every step's positions (K_ = 0), or positions and
+    // momenta at the checkpoints 0, K, 2K, ... plus K - 1 slots for the
+    // states between two checkpoints.  Force meshes: one per kept state.
+    const long long nck = K_ ? S_ / K_ + 1 : 0;
+    dtape_ = c.take<T>((K_ ? nck + K_ - 1 : S_ + 1) * 3 * P_);
+    ckp_ = K_ ? c.take<T>(nck * 3 * P_) : nullptr;
+    gtape_ = c.take<T>((tape_forces_ ? (K_ ? K_ : S_ + 1) : 1) * 3 * M_);
     p_ = c.take<T>(3 * P_);
     rhom_ = c.take<T>(M_);
     rhod_ = c.take<T>(P_);
@@ -283,7 +290,7 @@ class Engine final : public EngineBase {
     T* dd = static_cast<T*>(d);
     T* pp = static_cast<T*>(p);
     bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
-        ids(S_), state_ptrs(dslot(S_), p_), state_mptrs(dd, pp), 6, P_);
+        ids(S_), state_ptrs(dslot(S_), pslot(S_)), state_mptrs(dd, pp), 6, P_);
     IC_LAUNCHED();
   }
 
@@ -378,8 +385,23 @@ class Engine final : public EngineBase {
     return r;
   }
 
-  T* dslot(int n) const { return dtape_ + (long long)n * 3 * P_; }
-  T* gslot(int n) const { return tape_forces_ ? gtape_ + (long long)n * 3 * M_ : gtape_; }
+  // Slots of state n: positions d_n, the momentum the step from n starts
+  // with, and the force meshes at d_n.  With checkpoints, states K j sit in
+  // their own slots (d then the checkpoint area's first S/K + 1 slots) and
+  // the others share K - 1 segment slots.
+  T* dslot(int n) const {
+    if (!K_) return dtape_ + (long long)n * 3 * P_;
+    const long long nck = S_ / K_ + 1;
+    const long long j = n % K_ == 0 ? n / K_ : nck + n % K_ - 1;
+    return dtape_ + j * 3 * P_;
+  }
+  T* pslot(int n) const {
+    return K_ && n % K_ == 0 ? ckp_ + (long long)(n / K_) * 3 * P_ : p_;
+  }
+  T* gslot(int n) const {
+    if (!tape_forces_) return gtape_;
+    return gtape_ + (long long)(K_ ? n % K_ : n) * 3 * M_;
+  }
 
   void ek_fill_u32(uint32_t* x, uint32_t v, long long n) {
     fk::k_fill<uint32_t><<<grid_for(n, kThreads), kThreads, 0, st_>>>(x, v, n);
@@ -653,40 +675,68 @@ class Engine final : public EngineBase {
     lpt(s, tmpd_, tmpp_);
     keys_lattice(tmpd_, gmesh(), Lm_, nbm_);
     build_order(mesh_order(0));
-    scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), p_), 6, nullptr,
+    scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), pslot(0)), 6, nullptr,
             ids(0), dest(-1));
     force_mesh(0, gslot(0));
     for (int n = 0; n < S_; ++n) {
       zero_counts(nbm_);
-      {
-        auto sc = timer_.scope("pm_step", P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
-        bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), p_, gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
-            P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_, bcount_, bkey_,
-            brank_);
-        IC_LAUNCHED();
-      }
+      step(n, true);
       build_order(mesh_order(n + 1));
-      scatter(mesh_order(n + 1), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(n + 1), p_), 6,
-              ids(n), ids(n + 1), dest(n));
+      scatter(mesh_order(n + 1), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(n + 1), pslot(n + 1)),
+              6, ids(n), ids(n + 1), dest(n));
       force_mesh(n + 1, gslot(n + 1));
     }
+    seg_ = K_ ? S_ - S_ % K_ : 0;
     zero_counts(nbd_);
     {
       auto sc = timer_.scope("final_kick", P_ * (9.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
       bk::k_final_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-          dslot(S_), p_, gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_, gmesh(), Lm_,
-          items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
+          dslot(S_), pslot(S_), gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_, gmesh(),
+          Lm_, items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
       IC_LAUNCHED();
     }
     build_order(data_order());
-    scatter(data_order(), state_ptrs(dslot(S_), p_), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
-            dest(S_));
+    scatter(data_order(), state_ptrs(dslot(S_), pslot(S_)), state_mptrs(dsd_, psd_), 6, ids(S_),
+            dids_, dest(S_));
     fill(rhod_, T(0), P_);
     auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0));
     bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
                                                            Ld_, items(data_order(), dids_), rhod_);
     IC_LAUNCHED();
+  }
+
+  // Step n: readout of the forces at d_n, kick, drift into (tmpd_, tmpp_) in
+  // order n, with the block keys and ranks of the new positions when keyed.
+  void step(int n, bool keyed) {
+    auto sc = timer_.scope("pm_step", P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+    bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+        dslot(n), pslot(n), gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
+        P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_,
+        keyed ? bcount_ : nullptr, bkey_, brank_);
+    IC_LAUNCHED();
+  }
+
+  // Puts the states of the segment holding state n back in their slots:
+  // from checkpoint c = K floor(n / K), the steps c .. c + K - 2 run again in
+  // the orders the forward recorded (each new state goes to the next order
+  // through that step's recorded destinations, so ids and orders stay the
+  // ones the adjoint carries its cotangents through).  With taped forces
+  // the segment's force meshes are rebuilt too.
+  void restore_segment(int n) {
+    if (!K_) return;
+    const int c = n - n % K_;
+    if (c == seg_) return;
+    const int last = std::min(c + K_ - 1, S_);
+    for (int j = c; j < last; ++j) {
+      force_mesh(j, gslot(j));
+      step(j, false);
+      auto sc = timer_.scope("sort_replay", P_ * (12.0 * sizeT() + 4.0));
+      bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+          dest(j), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(j + 1), pslot(j + 1)), 6, P_);
+      IC_LAUNCHED();
+    }
+    if (tape_forces_) force_mesh(last, gslot(last));
+    seg_ = c;
   }
 
   bk::Ptrs<T> state_ptrs(const T* d, const T* p) const {
@@ -746,6 +796,7 @@ class Engine final : public EngineBase {
     const double sc_rho = -1.0 / ((double)P_ / (double)M_ * (double)M_);
     for (int n = S_; n >= 0; --n) {
       const T coef = static_cast<T>(co_.kick[n]);
+      restore_segment(n);
       T* g = gslot(n);
       if (!tape_forces_) force_mesh(n, g);
       const bk::Items it = items(mesh_order(n), ids(n));
@@ -869,6 +920,9 @@ class Engine final : public EngineBase {
   T* wtab_;
   cx<T>* pool_;
   T *phi_, *mu_, *dtape_, *gtape_, *p_, *rhom_, *rhod_, *seed_;
+  T* ckp_ = nullptr;   // checkpointed momenta (K_ > 0)
+  int K_ = 0;          // checkpoint spacing (0: every state kept)
+  int seg_ = -1;       // first state of the segment whose states are in their slots
   T *dbar_, *pbar_, *gbar_, *rhobar_;
   double *part_, *scal_;
   T *hist_S_, *hist_Y_, *dir_, *strial_, *gtrial_;

@@ -17,6 +17,19 @@ CASES = {
     "c1_16": dict(c=1, n_part=16, n_mesh=16, box=128.0),
     "radial32": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5, galaxies=2e4),
     "radial32_mesh2": dict(c=2, n_part=32, n_mesh=64, box=128.0, n_steps=5, galaxies=2e4),
+    # sigma8 = 6: shell crossing everywhere, most particles in a few dense cells,
+    # blocks with several work items (the regime of the first L-BFGS steps)
+    "clustered32": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5, galaxies=2e4,
+                        sigma8=6.0),
+    # the same with force meshes recomputed in the adjoint instead of taped
+    "clustered32_recompute": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5,
+                                  galaxies=2e4, sigma8=6.0, tape_forces=0),
+    # particle states kept at steps 0, 2, 4 only, the others replayed in the
+    # adjoint (segments of two states; with taped and with recomputed forces)
+    "clustered32_ckpt2": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5, galaxies=2e4,
+                              sigma8=6.0, ckpt_every=2),
+    "radial32_mesh2_ckpt3_recompute": dict(c=2, n_part=32, n_mesh=64, box=128.0, n_steps=5,
+                                           galaxies=2e4, ckpt_every=3, tape_forces=0),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}
@@ -87,3 +100,42 @@ def test_fp64_gpu_dot_product_identity():
     jv = mdl.jvp(s0, v)
     a, b = float(np.sum(jv * w)), float(np.sum(v * jtw))
     assert abs(a - b) <= 1e-10 * abs(a)
+
+
+# Checkpointed against fully taped adjoint on the same context settings: the
+# replayed steps repeat the forward's arithmetic, and only the order of the
+# global atomic additions in the recomputed paints can differ.
+TOL_CKPT = {"f32": 2e-5, "f64": 1e-11}
+TOL_CKPT_LOSS = {"f32": 1e-6, "f64": 1e-12}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_checkpointed_gradient_matches_taped_c2(prec):
+    require_gpu()
+    base = cfg_small(2)
+    base["nbar"] = inputs.nbar_for(base, inputs.response_field(base))
+    R = inputs.response_field(base)
+    sd = inputs.seeds(2)
+    s0 = inputs.white_noise(base["n_part"], sd["start"])
+    counts = None
+    grads = {}
+    for K, tf in ((0, 1), (5, 1), (3, 0)):
+        cfg = dict(base, ckpt_every=K, tape_forces=tf)
+        ctx = context(cfg, prec)
+        resp = to_dev(R, prec)
+        if counts is None:
+            ctx.set_observation(torch.zeros(ctx.grid, dtype=torch.int32, device=DEV), resp)
+            lam = to_np(ctx.forward(to_dev(inputs.white_noise(base["n_part"], sd["truth"]), prec),
+                                    delta=False, lam=True)["lambda"])
+            counts = inputs.poisson_counts(lam, R, base["r_min"], sd["counts"])
+        ctx.set_observation(torch.tensor(counts, dtype=torch.int32, device=DEV), resp)
+        L, g, _ = ctx.loss_and_grad(to_dev(s0, prec))
+        grads[(K, tf)] = (L, to_np(g))
+    L0, g0 = grads[(0, 1)]
+    for key in ((5, 1), (3, 0)):
+        L, g = grads[key]
+        err = rel_l2(g, g0)
+        print("ckpt_every %d tape_forces %d: loss rel %.3e gradient rel L2 %.3e"
+              % (key[0], key[1], abs(L - L0) / abs(L0), err))
+        assert abs(L - L0) <= TOL_CKPT_LOSS[prec] * abs(L0)
+        assert err <= TOL_CKPT[prec]

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.ic_abi_version() == 1
+    assert lib.ic_abi_version() == 2
     p = _lib.IcProblem()
     lib.ic_problem_defaults(ctypes.byref(p))
     assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
@@ -72,6 +72,24 @@ def test_workspace_sizes_and_validation(lib):
     assert rc == -1
     rc, _ = _size(lib, inputs.config(1), 7)
     assert rc == -1
+    rc, _ = _size(lib, inputs.config(1, ckpt_every=-1))
+    assert rc == -1
+
+
+def test_checkpoints_and_recomputed_forces_shrink_the_workspace(lib):
+    # 512^3 particles on a 1024^3 mesh, 20 steps: every state and force mesh
+    # taped does not fit one GPU; states every 5 steps with recomputed forces do
+    full = _size(lib, inputs.config(5, tape_forces=1, ckpt_every=0))[1]
+    forces = _size(lib, inputs.config(5, tape_forces=0, ckpt_every=0))[1]
+    both = _size(lib, inputs.config(5, tape_forces=0, ckpt_every=5))[1]
+    assert full > 288e9 > forces > both
+    # one position slot (3 fields) per state dropped, one momentum slot per
+    # checkpoint added: 21 states -> 5 checkpoints + 4 segment slots
+    P = 512 ** 3
+    assert forces - both == (21 - 9 - 5) * 3 * P * 4
+    # a spacing beyond the last step keeps state 0 and replays all the others
+    rc, far = _size(lib, inputs.config(1, ckpt_every=100))
+    assert rc == 0 and far == _size(lib, inputs.config(1, ckpt_every=6))[1]
 
 
 @pytest.mark.parametrize("om,steps", [(0.3, 5), (0.3, 10), (1.0, 4)])
