@@ -23,7 +23,7 @@ all zero at k = 0.
 import numpy as np
 from scipy import fft as sfft
 
-__all__ = ["rfft3", "irfft3", "wave_axes", "kgrid", "multiplier", "apply",
+__all__ = ["rfft3", "irfft3", "dft_modes", "wave_axes", "kgrid", "multiplier", "apply",
            "apply_sum"]
 
 _WORKERS = None
@@ -48,6 +48,33 @@ def rfft3(x):
 def irfft3(xk, n):
     """Inverse of rfft3 (applies 1/N^3); n is the real grid side."""
     return sfft.irfftn(xk, s=(n, n, n), workers=_workers())
+
+
+def dft_modes(x, modes, rows=1 << 16):
+    """Selected coefficients X(kx, ky, kz) of the unnormalised forward DFT,
+    X(k) = sum_r x(r) exp(-2 pi i k.r / N), summed straight from that
+    definition one axis at a time (z for all requested kz together, then y,
+    then x).  Costs O(N^3 * #kz) instead of a whole transform, for spot checks
+    of grids whose full FP64 transform is too large to hold.  Phases use the
+    exact integer product k r mod N."""
+    x = np.asarray(x)
+    n = x.shape[0]
+    r = np.arange(n, dtype=np.int64)
+    kzs = sorted({int(m[2]) for m in modes})
+    ph = 2.0 * np.pi * (np.outer(r, kzs) % n) / n           # (n, #kz)
+    cz, sz = np.cos(ph), np.sin(ph)
+    flat = x.reshape(n * n, n)
+    tz = np.empty((n * n, len(kzs)), dtype=np.complex128)
+    for i0 in range(0, n * n, rows):
+        blk = flat[i0:i0 + rows].astype(np.float64)
+        tz[i0:i0 + rows] = blk @ cz - 1j * (blk @ sz)
+    tz = tz.reshape(n, n, len(kzs))
+    out = np.empty(len(modes), dtype=np.complex128)
+    for i, (kx, ky, kz) in enumerate(modes):
+        ex = np.exp(-2j * np.pi * ((int(kx) * r) % n) / n)
+        ey = np.exp(-2j * np.pi * ((int(ky) * r) % n) / n)
+        out[i] = ex @ tz[:, :, kzs.index(int(kz))] @ ey
+    return out
 
 
 def wave_axes(n, box):

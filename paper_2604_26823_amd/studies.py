@@ -1,0 +1,211 @@
+"""Precision and scale studies of the hot path on one GPU (this library only).
+
+  python -m paper_2604_26823_amd.studies precision [--steps 1,2,...] [--out F]
+      256^3 particles on a 512^3 force mesh, 1000 Mpc/h, 20 KDK steps, radial
+      RSD and the 40x40 degree selection.  For each k the model is cut after
+      step k (the same linear-in-a time grid ending at a_k, so its first k
+      steps are the full run's); mock counts come from the FP64 model at a_k.
+      FP32 and FP64 instantiations of the same kernels evaluate density,
+      chi^2, loss and gradient at the same white noise; each record gives the
+      FP32 errors relative to FP64.
+  python -m paper_2604_26823_amd.studies scale [--iterations 50] [--ckpt-every 5]
+          [--tape-forces 0] [--profile] [--skip-f64] [--out F]
+      512^3 particles on a 1024^3 mesh, 2000 Mpc/h, 20 steps; particle states
+      kept every 5 steps and replayed in the adjoint, force meshes recomputed.
+      FP32: time per loss+gradient evaluation, peak device memory, then
+      projected L-BFGS iterations with rank-order matching every 20.  FP64:
+      one evaluation at the same start, compared with FP32.
+
+Every output line is one JSON record (also appended to --out)."""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if os.path.dirname(HERE) not in sys.path:
+    sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_2604_26823_amd import _lib, inputs  # noqa: E402
+
+
+def _emit(rec, out):
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if out:
+        with open(out, "a") as fh:
+            fh.write(line + "\n")
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _timed_eval(ctx, s, g, repeats=1):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(repeats):
+        L, g, terms = ctx.loss_and_grad(s, g)
+    torch.cuda.synchronize()
+    return L, g, terms, 1e3 * (time.perf_counter() - t) / repeats
+
+
+def _observe(ctx, R, counts):
+    import torch
+    ctx.set_observation(torch.tensor(counts, dtype=torch.int32, device=ctx.device),
+                        torch.tensor(R, dtype=ctx.dtype, device=ctx.device))
+
+
+def _mock_counts(ctx, cfg, R, seed_cfg):
+    """Poisson counts of the truth white noise through ctx's forward model."""
+    import torch
+    sd = inputs.seeds(seed_cfg)
+    s_true = torch.tensor(inputs.white_noise(cfg["n_part"], sd["truth"]), dtype=ctx.dtype,
+                          device=ctx.device)
+    _observe(ctx, R, np.zeros(R.shape, dtype=np.int32))
+    lam = ctx.forward(s_true, delta=False, lam=True)["lambda"].double().cpu().numpy()
+    return inputs.poisson_counts(lam, R, cfg["r_min"], sd["counts"])
+
+
+def precision(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    base = inputs.config(4)
+    R = inputs.response_field(base)
+    base["nbar"] = inputs.nbar_for(base, R)
+    s0 = inputs.white_noise(base["n_part"], inputs.seeds(4)["start"])
+    steps = [int(k) for k in a.steps.split(",")] if a.steps else range(1, base["n_steps"] + 1)
+    for k in steps:
+        ak = base["a_init"] + k * (base["a_final"] - base["a_init"]) / base["n_steps"]
+        cfg = dict(base, n_steps=k, a_final=ak)
+        res = {}
+        counts = None
+        for prec in ("f64", "f32"):
+            ctx = Context(cfg, prec, "cuda:0")
+            if counts is None:
+                counts = _mock_counts(ctx, cfg, R, 4)
+            _observe(ctx, R, counts)
+            s = torch.tensor(s0, dtype=ctx.dtype, device=ctx.device)
+            delta = ctx.forward(s, delta=True)["delta"].double().cpu().numpy()
+            L, g, terms, ms = _timed_eval(ctx, s, None)
+            L, g, terms, ms = _timed_eval(ctx, s, g)
+            res[prec] = dict(delta=delta, L=L, chi2=terms["chi2"], g=g.double().cpu().numpy(),
+                             ms=ms)
+            ctx.close()
+            del ctx, s, g
+            torch.cuda.empty_cache()
+        r32, r64 = res["f32"], res["f64"]
+        _emit(dict(study="precision", workload="256^3 particles, 512^3 mesh, 1000 Mpc/h",
+                   step=k, a=ak, density_rel_l2=_rel(r32["delta"], r64["delta"]),
+                   chi2_f64=r64["chi2"], chi2_rel=abs(r32["chi2"] - r64["chi2"]) / r64["chi2"],
+                   loss_rel=abs(r32["L"] - r64["L"]) / r64["L"],
+                   grad_rel_l2=_rel(r32["g"], r64["g"]), eval_ms_f32=r32["ms"],
+                   eval_ms_f64=r64["ms"]), a.out)
+
+
+def scale(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    cfg = inputs.config(5, ckpt_every=a.ckpt_every, tape_forces=a.tape_forces)
+    R = inputs.response_field(cfg)
+    cfg["nbar"] = inputs.nbar_for(cfg, R)
+    s_start = inputs.white_noise(cfg["n_part"], inputs.seeds(5)["start"])
+    work = ("512^3 particles, 1024^3 mesh, 2000 Mpc/h, 20 steps, ckpt_every %d, tape_forces %d"
+            % (a.ckpt_every, a.tape_forces))
+    torch.cuda.reset_peak_memory_stats()
+    ctx = Context(cfg, "f32", "cuda:0")
+    counts = _mock_counts(ctx, cfg, R, 5)
+    _observe(ctx, R, counts)
+    s = torch.tensor(s_start, dtype=ctx.dtype, device=ctx.device)
+    ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+    s_proj = s.double().cpu().numpy()
+    delta32 = ctx.forward(s, delta=True)["delta"].double().cpu().numpy()
+    L32, g, terms32, _ = _timed_eval(ctx, s, None)
+    L32, g, terms32, ms32 = _timed_eval(ctx, s, g, repeats=a.repeats)
+    g32 = g.double().cpu().numpy()
+    if a.profile:
+        ctx.timing(True)
+        ctx.loss_and_grad(s, g)
+        rows = ctx.timing_report()
+        ctx.timing(False)
+        for r in sorted(rows, key=lambda r: -r["ms"])[:20]:
+            _emit(dict(study="scale", workload=work, precision="f32", kernel=r["name"],
+                       count=r["count"], ms=r["ms"]), a.out)
+    free, total = torch.cuda.mem_get_info()
+    _emit(dict(study="scale", workload=work, precision="f32", eval_ms=ms32, loss=L32,
+               chi2=terms32["chi2"], workspace_gb=ctx.ws_bytes / 1e9,
+               peak_allocated_gb=torch.cuda.max_memory_allocated() / 1e9,
+               device_used_gb=(total - free) / 1e9, device_total_gb=total / 1e9), a.out)
+    L = L32
+    t0 = time.perf_counter()
+    evals = 0
+    for it in range(a.iterations):
+        t = time.perf_counter()
+        L, info = ctx.lbfgs_step(s, g, L, it)
+        evals += info["evaluations"]
+        rom = None
+        if (it + 1) % 20 == 0:
+            rom = ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL
+                                        | _lib.IC_ROM_FOURIER, event=it + 1)
+            ctx.lbfgs_reset()
+            L, g, _ = ctx.loss_and_grad(s, g)
+            evals += 1
+        torch.cuda.synchronize()
+        _emit(dict(study="scale", workload=work, iteration=it, loss=L, eps=info["eps"],
+                   evaluations=info["evaluations"], rom=rom,
+                   seconds=time.perf_counter() - t), a.out)
+    if a.iterations:
+        _emit(dict(study="scale", workload=work, precision="f32", iterations=a.iterations,
+                   evaluations=evals, seconds=time.perf_counter() - t0,
+                   peak_allocated_gb=torch.cuda.max_memory_allocated() / 1e9), a.out)
+    ctx.close()
+    del ctx, s, g
+    torch.cuda.empty_cache()
+    if a.skip_f64:
+        return
+    torch.cuda.reset_peak_memory_stats()
+    ctx = Context(cfg, "f64", "cuda:0")
+    _observe(ctx, R, counts)
+    s = torch.tensor(s_proj, dtype=ctx.dtype, device=ctx.device)
+    delta64 = ctx.forward(s, delta=True)["delta"].double().cpu().numpy()
+    L64, g, terms64, ms64 = _timed_eval(ctx, s, None)
+    free, total = torch.cuda.mem_get_info()
+    _emit(dict(study="scale", workload=work, precision="f64", eval_ms=ms64, loss=L64,
+               chi2=terms64["chi2"], workspace_gb=ctx.ws_bytes / 1e9,
+               peak_allocated_gb=torch.cuda.max_memory_allocated() / 1e9,
+               device_used_gb=(total - free) / 1e9,
+               density_rel_l2_f32=_rel(delta32, delta64),
+               loss_rel_f32=abs(L32 - L64) / abs(L64),
+               chi2_rel_f32=abs(terms32["chi2"] - terms64["chi2"]) / terms64["chi2"],
+               grad_rel_l2_f32=_rel(g32, g.double().cpu().numpy())), a.out)
+    ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    pr = sub.add_parser("precision")
+    pr.add_argument("--steps", default="")
+    sc = sub.add_parser("scale")
+    sc.add_argument("--iterations", type=int, default=50)
+    sc.add_argument("--repeats", type=int, default=3)
+    sc.add_argument("--ckpt-every", type=int, default=5)
+    sc.add_argument("--tape-forces", type=int, default=0)
+    sc.add_argument("--profile", action="store_true")
+    sc.add_argument("--skip-f64", action="store_true")
+    for p in (pr, sc):
+        p.add_argument("--out", default="")
+    a = ap.parse_args()
+    (precision if a.mode == "precision" else scale)(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,116 @@
+"""Checks at the 512^3 and 1024^3 force-mesh sizes (GPU): the mesh transforms of
+the 256^3-on-512^3 and 512^3-on-1024^3 problems, and the first PM steps of the
+256^3-on-512^3 problem (20 steps, 1000 Mpc/h) against the oracle.
+
+The FP64 oracle cannot run whole evaluations at these sizes in test time, so
+parity uses outputs it computes one by one -- single DFT coefficients summed
+from the definition, the density after the first two of the twenty steps --
+and properties that hold at any size (Parseval's identity, the round trip).
+Each context is closed when its test ends: a 1024^3 FP64 context holds
+~170 GB of workspace."""
+import numpy as np
+import pytest
+
+from gpu_common import DEV, rel_l2, require_gpu, to_np, torch
+from oracle import fourier
+from paper_2604_26823_amd import _lib, inputs
+from paper_2604_26823_amd.api import Context
+
+pytestmark = pytest.mark.gpu
+
+# Spot coefficients: error over |x|_2 (the rms size of a coefficient); an FFT
+# of N^3 points carries ~log2(N^3) roundings of the working precision.
+TOL_MODE = {"f32": 5e-6, "f64": 1e-13}
+TOL_ROUNDTRIP = {"f32": 3e-6, "f64": 1e-13}
+TOL_PARSEVAL = {"f32": 1e-5, "f64": 1e-12}
+TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
+
+
+def _mesh_context(n, prec):
+    # smallest problem with an n^3 force mesh: one step, forces recomputed
+    cfg = inputs.config(1, n_part=n // 2, n_mesh=n, box=4.0 * n, n_steps=1, tape_forces=0,
+                        lbfgs_m=1)
+    return Context(cfg, prec, DEV)
+
+
+def _modes(n, rng, count=10):
+    h = n // 2
+    fixed = [(0, 0, 0), (h, h, h), (1, n - 1, h), (n - 1, 1, 0), (h, 0, 1), (3, h, h - 1)]
+    rand = [(int(rng.integers(n)), int(rng.integers(n)), int(rng.integers(h + 1)))
+            for _ in range(count)]
+    return fixed + rand
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n", [512, 1024])
+def test_mesh_fft_spot_modes_parseval_and_round_trip(n, prec):
+    require_gpu()
+    free, total = torch.cuda.mem_get_info()
+    print("device memory free %.1f of %.1f GB" % (free / 1e9, total / 1e9), flush=True)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n, n, n), dtype=np.float32)
+    ctx = _mesh_context(n, prec)
+    try:
+        xd = torch.from_numpy(x).to(DEV).to(ctx.dtype)
+        X = ctx.rfft(xd, grid=_lib.IC_GRID_MESH)
+        modes = _modes(n, rng)
+        idx = torch.tensor(modes, dtype=torch.long, device=DEV)
+        got = X[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().astype(np.complex128)
+        xn = float(torch.linalg.vector_norm(xd.double()))
+        # Parseval on the half spectrum: planes kz = 0 and N/2 once, the rest twice
+        p2 = X.abs().double().pow_(2)
+        spec = 2.0 * p2.sum() - p2[:, :, 0].sum() - p2[:, :, n // 2].sum()
+        del p2
+        parseval = abs(float(spec) / n ** 3 - xn * xn) / (xn * xn)
+        y = ctx.irfft(X, grid=_lib.IC_GRID_MESH)
+        del X
+        rt = float(torch.linalg.vector_norm((y - xd).double())) / xn
+        del y, xd
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = fourier.dft_modes(x, modes)
+    err = np.max(np.abs(got - ref)) / xn
+    print("n %d %s: spot modes %.2e, Parseval %.2e, round trip %.2e"
+          % (n, prec, err, parseval, rt))
+    assert err <= TOL_MODE[prec]
+    assert parseval <= TOL_PARSEVAL[prec]
+    assert rt <= TOL_ROUNDTRIP[prec]
+
+
+def _c4_golden():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "c4_density_two_steps.txt")
+    rows = np.loadtxt(path, comments="#")
+    return rows[:, 0].astype(np.int64), rows[:, 1]
+
+
+def test_c4_density_after_two_steps_matches_oracle():
+    """256^3 particles on the 512^3 mesh, the first two of twenty steps (the same
+    time grid cut at a_2 = a_init + 2 (1 - a_init) / 20), radial RSD and the
+    data paint at a_2, FP32 and FP64 against the oracle's values at 4096 sampled
+    cells (tests/golden/make_c4_density.py), plus mass conservation over the
+    whole grid."""
+    require_gpu()
+    base = inputs.config(4)
+    a2 = base["a_init"] + 2 * (base["a_final"] - base["a_init"]) / base["n_steps"]
+    cfg = dict(base, n_steps=2, a_final=a2)
+    s0 = inputs.white_noise(cfg["n_part"], inputs.seeds(4)["start"])
+    idx, ref = _c4_golden()
+    for prec in ("f64", "f32"):
+        ctx = Context(cfg, prec, DEV)
+        try:
+            out = ctx.forward(torch.tensor(s0, dtype=ctx.dtype, device=DEV), delta=True)
+            got = to_np(out["delta"]).ravel()
+        finally:
+            ctx.close()
+            del ctx
+            torch.cuda.empty_cache()
+        err = rel_l2(got[idx], ref)
+        mass = abs(got.sum()) / got.size
+        print("c4 after two steps, %s: sampled density rel L2 %.3e, mean %.2e" % (prec, err, mass))
+        assert err <= TOL_DENS[prec]
+        assert mass <= (1e-5 if prec == "f32" else 1e-12)

@@ -33,6 +33,19 @@ def test_rfft_matches_brute_force_dft_8():
     assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+def test_dft_modes_match_brute_force_and_full_transform():
+    x = np.random.default_rng(11).standard_normal((8, 8, 8))
+    modes = [(0, 0, 0), (7, 1, 4), (4, 4, 4), (3, 6, 2), (1, 0, 1)]
+    ref = brute_rdft(x)
+    got = F.dft_modes(x.astype(np.float32), modes, rows=5)
+    x32 = F.rfft3(x.astype(np.float32))
+    for m, g in zip(modes, got):
+        assert abs(g - x32[m]) <= 1e-12 * np.max(np.abs(x32))
+    got = F.dft_modes(x, modes)
+    for m, g in zip(modes, got):
+        assert abs(g - ref[m]) <= 1e-13 * np.max(np.abs(ref))
+
+
 def test_parseval_and_roundtrip():
     x = np.random.default_rng(2).standard_normal((16, 16, 16))
     xk = F.rfft3(x)
