@@ -40,7 +40,7 @@ constexpr int kB = 1 << kLB;           // block side
 constexpr int kW = kB + 1;             // window side
 constexpr int kWin = kW * kW * kW;     // window cells (729)
 constexpr int kThreads = 256;
-constexpr int kPer = 2;                // particles per thread
+constexpr int kPer = 4;                // particles per thread
 constexpr int kChunk = kThreads * kPer;  // particles per work item
 
 // Blocks of one grid of side 2^lm (lm >= 3).
@@ -104,15 +104,22 @@ __device__ __forceinline__ unsigned win_cell(const int o[3], int k, const Layout
          (static_cast<unsigned>(o[2] + kz) & mask);
 }
 
-// Rank of this lane's particle within its block.  The lanes of the
-// wavefront are grouped by key with ballots first; then each group's first
-// lane adds the group size to the block count, all groups in the same
-// atomic instruction, so the wavefront waits for one atomic round trip
-// whatever the number of distinct keys.  The lanes of a group take
-// consecutive ranks.  Every lane of the wavefront must call it; inactive
-// lanes pass active = false and get 0.
-__device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
-                                                  unsigned* __restrict__ count) {
+// Rank of this lane's particle within its block, in two halves so that a
+// thread can have the atomics of several particles in flight at once:
+// rank_issue groups the lanes of the wavefront by key with ballots, then each
+// group's first lane adds the group size to the block count, all groups in
+// the same atomic instruction (one round trip whatever the number of
+// distinct keys); rank_finish reads the group's base from its first lane.
+// The lanes of a group take consecutive ranks.  Every lane of the wavefront
+// must call both; inactive lanes pass active = false and get 0.
+struct RankTicket {
+  unsigned base;  // atomic result, valid in group leaders
+  int leader;
+  unsigned off;
+};
+
+__device__ __forceinline__ RankTicket rank_issue(unsigned key, bool active,
+                                                 unsigned* __restrict__ count) {
   const int lane = static_cast<int>(threadIdx.x & 63);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   unsigned long long todo = __ballot(active);
@@ -129,10 +136,19 @@ __device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
     }
     todo &= ~same;
   }
-  unsigned base = 0;
-  if (group) base = atomicAdd(count + key, group);
-  base = static_cast<unsigned>(__shfl(static_cast<int>(base), my_leader, 64));
-  return active ? base + my_off : 0u;
+  RankTicket t{0u, my_leader, my_off};
+  if (group) t.base = atomicAdd(count + key, group);
+  return t;
+}
+
+__device__ __forceinline__ unsigned rank_finish(const RankTicket& t, bool active) {
+  const unsigned base = static_cast<unsigned>(__shfl(static_cast<int>(t.base), t.leader, 64));
+  return active ? base + t.off : 0u;
+}
+
+__device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
+                                                  unsigned* __restrict__ count) {
+  return rank_finish(rank_issue(key, active, count), active);
 }
 
 // ---------------------------------------------------------------- sorting
@@ -428,16 +444,21 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
   __shared__ double acc[kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
+  bool ok[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
+    long long a;
+    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
+    if (ok[k]) pk::load3(d, P, a, dsp[k]);
+  }
   zero_window(acc, 1);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    if (!item_slot(m, it, k, lp, a, idx)) continue;
-    T dsp[3];
-    pk::load3(d, P, a, dsp);
-    const Stencil<T> s = wrapped_stencil(idx, dsp, g);
+    if (!ok[k]) continue;
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], g);
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
       atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
     });
@@ -456,19 +477,26 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
   __shared__ double acc[3 * kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
+  bool ok[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], vv[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
+    long long a;
+    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a, dsp[k]);
+    pk::load3(v, P, a, vv[k]);
+  }
   zero_window(acc, 3);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    if (!item_slot(m, it, k, lp, a, idx)) continue;
-    T dsp[3], vv[3];
-    pk::load3(d, P, a, dsp);
-    pk::load3(v, P, a, vv);
-    const double v0 = static_cast<double>(coef * vv[0]), v1 = static_cast<double>(coef * vv[1]),
-                 v2 = static_cast<double>(coef * vv[2]);
-    const Stencil<T> s = wrapped_stencil(idx, dsp, g);
+    if (!ok[k]) continue;
+    const double v0 = static_cast<double>(coef * vv[k][0]),
+                 v1 = static_cast<double>(coef * vv[k][1]),
+                 v2 = static_cast<double>(coef * vv[k][2]);
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], g);
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
       const int c = win_index(m.o, cx, cy, cz);
       const double wd = static_cast<double>(w);
@@ -493,40 +521,53 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
   __shared__ T lds[3 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
+  long long a[kPer];
+  bool ok[kPer];
+  unsigned b[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
+    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a[k], dsp[k]);
+    pk::load3(p, P, a[k], mom[k]);
+  }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    const bool ok = item_slot(m, it, k, lp, a, idx);
-    unsigned b = 0;
-    if (ok) {
-      T dsp[3], mom[3], F[3] = {0, 0, 0};
-      pk::load3(d, P, a, dsp);
-      pk::load3(p, P, a, mom);
-      const Stencil<T> s = wrapped_stencil(idx, dsp, gr);
-      pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
-        const int c = win_index(m.o, cx, cy, cz);
-        F[0] += w * lds[c];
-        F[1] += w * lds[kWin + c];
-        F[2] += w * lds[2 * kWin + c];
-      });
+    b[k] = 0;
+    if (!ok[k]) continue;
+    T F[3] = {0, 0, 0};
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], gr);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      const int c = win_index(m.o, cx, cy, cz);
+      F[0] += w * lds[c];
+      F[1] += w * lds[kWin + c];
+      F[2] += w * lds[2 * kWin + c];
+    });
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        mom[q] += kick * F[q];
-        pn[q * P + a] = mom[q];
-        dsp[q] += drift * mom[q];
-        dn[q * P + a] = dsp[q];
-      }
-      Stencil<T> s2 = pk::stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
-      b = block_of(s2, L);
+    for (int q = 0; q < 3; ++q) {
+      mom[k][q] += kick * F[q];
+      pn[q * P + a[k]] = mom[k][q];
+      dsp[k][q] += drift * mom[k][q];
+      dn[q * P + a[k]] = dsp[k][q];
     }
-    if (!count) continue;
-    const unsigned r = rank_in_block(b, ok, count);
-    if (ok) {
-      key[a] = b;
-      rank[a] = r;
+    Stencil<T> s2 = pk::stencil(idx[k], gr.ratio, dsp[k], gr.inv_cell, gr.cell);
+    b[k] = block_of(s2, L);
+  }
+  if (!count) return;
+  // all of this thread's rank atomics in flight before the first is used
+  RankTicket t[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) t[k] = rank_issue(b[k], ok[k], count);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const unsigned r = rank_finish(t[k], ok[k]);
+    if (ok[k]) {
+      key[a[k]] = b[k];
+      rank[a[k]] = r;
     }
   }
 }
@@ -588,38 +629,50 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
   __shared__ T lds[3 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
+  long long a[kPer];
+  bool ok[kPer];
+  unsigned b[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
+    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a[k], dsp[k]);
+    pk::load3(p, P, a[k], mom[k]);
+  }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    const bool ok = item_slot(m, it, k, lp, a, idx);
-    unsigned b = 0;
-    if (ok) {
-      T dsp[3], mom[3], F[3] = {0, 0, 0}, ds[3];
-      pk::load3(d, P, a, dsp);
-      pk::load3(p, P, a, mom);
-      const Stencil<T> s = wrapped_stencil(idx, dsp, gm);
-      pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
-        const int c = win_index(m.o, cx, cy, cz);
-        F[0] += w * lds[c];
-        F[1] += w * lds[kWin + c];
-        F[2] += w * lds[2 * kWin + c];
-      });
+    b[k] = 0;
+    if (!ok[k]) continue;
+    T F[3] = {0, 0, 0}, ds[3];
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], gm);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      const int c = win_index(m.o, cx, cy, cz);
+      F[0] += w * lds[c];
+      F[1] += w * lds[kWin + c];
+      F[2] += w * lds[2 * kWin + c];
+    });
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        mom[q] += kick * F[q];
-        p[q * P + a] = mom[q];
-      }
-      pk::rsd_shift(rsd, idx, dsp, mom, ds);
-      Stencil<T> s2 = pk::stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
-      b = block_of(s2, Ld);
+    for (int q = 0; q < 3; ++q) {
+      mom[k][q] += kick * F[q];
+      p[q * P + a[k]] = mom[k][q];
     }
-    const unsigned r = rank_in_block(b, ok, count);
-    if (ok) {
-      key[a] = b;
-      rank[a] = r;
+    pk::rsd_shift(rsd, idx[k], dsp[k], mom[k], ds);
+    Stencil<T> s2 = pk::stencil(idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
+    b[k] = block_of(s2, Ld);
+  }
+  RankTicket t[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) t[k] = rank_issue(b[k], ok[k], count);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const unsigned r = rank_finish(t[k], ok[k]);
+    if (ok[k]) {
+      key[a[k]] = b[k];
+      rank[a[k]] = r;
     }
   }
 }
@@ -634,18 +687,25 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
   __shared__ double acc[kWin];
   Item m;
   if (!item_of<false>(it, Ld, m)) return;
+  bool ok[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
+    long long a;
+    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a, dsp[k]);
+    pk::load3(p, P, a, mom[k]);
+  }
   zero_window(acc, 1);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    if (!item_slot(m, it, k, lp, a, idx)) continue;
-    T dsp[3], mom[3], ds[3];
-    pk::load3(d, P, a, dsp);
-    pk::load3(p, P, a, mom);
-    pk::rsd_shift(rsd, idx, dsp, mom, ds);
-    const Stencil<T> s = wrapped_stencil(idx, ds, gd);
+    if (!ok[k]) continue;
+    T ds[3];
+    pk::rsd_shift(rsd, idx[k], dsp[k], mom[k], ds);
+    const Stencil<T> s = wrapped_stencil(idx[k], ds, gd);
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
       atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
     });
@@ -664,18 +724,25 @@ __global__ __launch_bounds__(kThreads) void k_data_adjoint_b(
   __shared__ T lds[kWin];
   Item m;
   if (!item_of<true>(it, Ld, m)) return;
+  long long a[kPer];
+  bool ok[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], mom[kPer][3];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
+    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, a[k], dsp[k]);
+    pk::load3(p, P, a[k], mom[k]);
+  }
   load_window<T>(m.o, Ld, Ptrs<T>{{rho_bar}}, 1, lds);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    long long a;
-    int idx[3];
-    if (!item_slot(m, it, k, lp, a, idx)) continue;
-    T dsp[3], mom[3], ds[3];
-    pk::load3(d, P, a, dsp);
-    pk::load3(p, P, a, mom);
-    pk::rsd_shift(rsd, idx, dsp, mom, ds);
-    const Stencil<T> s = wrapped_stencil(idx, ds, gd);
+    if (!ok[k]) continue;
+    T ds[3];
+    pk::rsd_shift(rsd, idx[k], dsp[k], mom[k], ds);
+    const Stencil<T> s = wrapped_stencil(idx[k], ds, gd);
     T xb[3] = {0, 0, 0};
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T, T d0, T d1, T d2) {
       const T r = lds[win_index(m.o, cx, cy, cz)];
@@ -686,11 +753,11 @@ __global__ __launch_bounds__(kThreads) void k_data_adjoint_b(
 #pragma unroll
     for (int q = 0; q < 3; ++q) xb[q] *= gd.inv_cell;
     T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
-    pk::rsd_transpose(rsd, idx, dsp, mom, xb, db, pb);
+    pk::rsd_transpose(rsd, idx[k], dsp[k], mom[k], xb, db, pb);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      dbar[q * P + a] = db[q];
-      pbar[q * P + a] = pb[q];
+      dbar[q * P + a[k]] = db[q];
+      pbar[q * P + a[k]] = pb[q];
     }
   }
 }

@@ -708,7 +708,8 @@ class Engine final : public EngineBase {
   // Step n: readout of the forces at d_n, kick, drift into (tmpd_, tmpp_) in
   // order n, with the block keys and ranks of the new positions when keyed.
   void step(int n, bool keyed) {
-    auto sc = timer_.scope("pm_step", P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+    auto sc = timer_.scope(keyed ? "pm_step" : "pm_step_replay",
+                           P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
     bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
         dslot(n), pslot(n), gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
         P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_,
