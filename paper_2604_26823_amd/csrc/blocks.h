@@ -104,51 +104,114 @@ __device__ __forceinline__ unsigned win_cell(const int o[3], int k, const Layout
          (static_cast<unsigned>(o[2] + kz) & mask);
 }
 
-// Rank of this lane's particle within its block, in two halves so that a
-// thread can have the atomics of several particles in flight at once:
-// rank_issue groups the lanes of the wavefront by key with ballots, then each
-// group's first lane adds the group size to the block count, all groups in
-// the same atomic instruction (one round trip whatever the number of
-// distinct keys); rank_finish reads the group's base from its first lane.
-// The lanes of a group take consecutive ranks.  Every lane of the wavefront
-// must call both; inactive lanes pass active = false and get 0.
+// Lanes of the wavefront grouped by key with ballots: each active lane gets
+// its group's first lane (leader) and its offset within the group, and the
+// leader also gets the group size (0 elsewhere).  Every lane of the wavefront
+// must call it; inactive lanes pass active = false.
 struct RankTicket {
-  unsigned base;  // atomic result, valid in group leaders
+  unsigned base;  // the leader's reservation (atomic result), valid in leaders
   int leader;
   unsigned off;
 };
 
-__device__ __forceinline__ RankTicket rank_issue(unsigned key, bool active,
-                                                 unsigned* __restrict__ count) {
+__device__ __forceinline__ RankTicket group_by_key(unsigned key, bool active, unsigned& size) {
   const int lane = static_cast<int>(threadIdx.x & 63);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   unsigned long long todo = __ballot(active);
-  int my_leader = 0;
-  unsigned my_off = 0, group = 0;
+  RankTicket t{0u, 0, 0u};
+  size = 0;
   while (todo) {
     const int leader = __ffsll(static_cast<long long>(todo)) - 1;
     const unsigned k = static_cast<unsigned>(__shfl(static_cast<int>(key), leader, 64));
     const unsigned long long same = __ballot(active && key == k);
-    if (lane == leader) group = static_cast<unsigned>(__popcll(same));
+    if (lane == leader) size = static_cast<unsigned>(__popcll(same));
     if (active && key == k) {
-      my_leader = leader;
-      my_off = static_cast<unsigned>(__popcll(same & below));
+      t.leader = leader;
+      t.off = static_cast<unsigned>(__popcll(same & below));
     }
     todo &= ~same;
   }
-  RankTicket t{0u, my_leader, my_off};
-  if (group) t.base = atomicAdd(count + key, group);
   return t;
 }
 
-__device__ __forceinline__ unsigned rank_finish(const RankTicket& t, bool active) {
+// Rank of this lane's particle within its block: each group's leader adds
+// the group size to the block count, all groups in the same atomic
+// instruction (one round trip whatever the number of distinct keys), and the
+// lanes of a group take consecutive ranks from the leader's result.
+// Inactive lanes get 0.
+__device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
+                                                  unsigned* __restrict__ count) {
+  unsigned size;
+  RankTicket t = group_by_key(key, active, size);
+  if (size) t.base = atomicAdd(count + key, size);
   const unsigned base = static_cast<unsigned>(__shfl(static_cast<int>(t.base), t.leader, 64));
   return active ? base + t.off : 0u;
 }
 
-__device__ __forceinline__ unsigned rank_in_block(unsigned key, bool active,
-                                                  unsigned* __restrict__ count) {
-  return rank_finish(rank_issue(key, active, count), active);
+// Ranks aggregated over a workgroup whose particles all start in block b0:
+// after a drift nearly every particle is in b0 or one of its 26 neighbours,
+// so the wavefront groups reserve offsets on 27 LDS counters, one thread per
+// non-empty counter then reserves the workgroup's range in that block's
+// global count with one atomic, and each particle's rank is that base plus
+// its offset.  Keys farther away keep the per-wavefront global atomic.
+constexpr int kNbr = 27;
+
+// Neighbour slot (0..26) of block key relative to block b0, or kNbr if the
+// blocks are not adjacent (periodic block grid of side 2^lnb).
+__device__ __forceinline__ int neighbour_slot(unsigned b0, unsigned key, const Layout& L) {
+  const unsigned m = (1u << L.lnb) - 1;
+  int slot = 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int sh = (2 - ax) * L.lnb;
+    const unsigned d = ((key >> sh) - (b0 >> sh)) & m;
+    int dd;
+    if (d <= 1u) dd = static_cast<int>(d);
+    else if (d == m) dd = -1;
+    else return kNbr;
+    slot = slot * 3 + dd + 1;
+  }
+  return slot;
+}
+
+// Block key of neighbour slot s of block b0.
+__device__ __forceinline__ unsigned neighbour_key(unsigned b0, int s, const Layout& L) {
+  const unsigned m = (1u << L.lnb) - 1;
+  const int dd[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
+  unsigned key = 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int sh = (2 - ax) * L.lnb;
+    key |= ((((b0 >> sh) & m) + static_cast<unsigned>(dd[ax])) & m) << sh;
+  }
+  return key;
+}
+
+// First half: each wavefront group's leader reserves the group's offsets,
+// on the workgroup counter wcnt[slot] for neighbour keys, else on the global
+// count; all of a thread's reservations can be in flight at once.
+__device__ __forceinline__ RankTicket rank_issue_wg(unsigned key, int slot, bool active,
+                                                    unsigned* __restrict__ count,
+                                                    unsigned* wcnt) {
+  unsigned size;
+  RankTicket t = group_by_key(key, active, size);
+  if (size) t.base = slot < kNbr ? atomicAdd(wcnt + slot, size) : atomicAdd(count + key, size);
+  return t;
+}
+
+// Between the halves (with barriers around it): the workgroup's ranges.
+__device__ __forceinline__ void rank_reserve_wg(unsigned b0, const Layout& L,
+                                                unsigned* __restrict__ count, const unsigned* wcnt,
+                                                unsigned* wbase) {
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < kNbr && wcnt[t]) wbase[t] = atomicAdd(count + neighbour_key(b0, t, L), wcnt[t]);
+}
+
+__device__ __forceinline__ unsigned rank_finish_wg(const RankTicket& t, int slot, bool active,
+                                                   const unsigned* wbase) {
+  unsigned base = static_cast<unsigned>(__shfl(static_cast<int>(t.base), t.leader, 64));
+  if (slot < kNbr) base += wbase[slot];
+  return active ? base + t.off : 0u;
 }
 
 // ---------------------------------------------------------------- sorting
@@ -558,13 +621,23 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
     b[k] = block_of(s2, L);
   }
   if (!count) return;
-  // all of this thread's rank atomics in flight before the first is used
+  // ranks aggregated over the workgroup (see rank_issue_wg)
+  __shared__ unsigned wcnt[kNbr], wbase[kNbr];
+  if (threadIdx.x < kNbr) wcnt[threadIdx.x] = 0;
+  __syncthreads();
   RankTicket t[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) t[k] = rank_issue(b[k], ok[k], count);
+  int slot[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const unsigned r = rank_finish(t[k], ok[k]);
+    slot[k] = neighbour_slot(m.b, b[k], L);
+    t[k] = rank_issue_wg(b[k], slot[k], ok[k], count, wcnt);
+  }
+  __syncthreads();
+  rank_reserve_wg(m.b, L, count, wcnt, wbase);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const unsigned r = rank_finish_wg(t[k], slot[k], ok[k], wbase);
     if (ok[k]) {
       key[a[k]] = b[k];
       rank[a[k]] = r;
@@ -664,12 +737,28 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
     Stencil<T> s2 = pk::stencil(idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);
     b[k] = block_of(s2, Ld);
   }
+  // ranks aggregated over the workgroup around the data-grid block that
+  // holds this mesh block's origin (see rank_issue_wg)
+  const int rs = L.lm - Ld.lm;
+  const unsigned b0 = ((static_cast<unsigned>(m.o[0] >> rs) >> kLB) << (2 * Ld.lnb)) |
+                      ((static_cast<unsigned>(m.o[1] >> rs) >> kLB) << Ld.lnb) |
+                      (static_cast<unsigned>(m.o[2] >> rs) >> kLB);
+  __shared__ unsigned wcnt[kNbr], wbase[kNbr];
+  if (threadIdx.x < kNbr) wcnt[threadIdx.x] = 0;
+  __syncthreads();
   RankTicket t[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) t[k] = rank_issue(b[k], ok[k], count);
+  int slot[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    const unsigned r = rank_finish(t[k], ok[k]);
+    slot[k] = neighbour_slot(b0, b[k], Ld);
+    t[k] = rank_issue_wg(b[k], slot[k], ok[k], count, wcnt);
+  }
+  __syncthreads();
+  rank_reserve_wg(b0, Ld, count, wcnt, wbase);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const unsigned r = rank_finish_wg(t[k], slot[k], ok[k], wbase);
     if (ok[k]) {
       key[a[k]] = b[k];
       rank[a[k]] = r;
