@@ -30,6 +30,10 @@ CASES = {
                               sigma8=6.0, ckpt_every=2),
     "radial32_mesh2_ckpt3_recompute": dict(c=2, n_part=32, n_mesh=64, box=128.0, n_steps=5,
                                            galaxies=2e4, ckpt_every=3, tape_forces=0),
+    # one step in a 16 Mpc/h box: ~1.4% of the particles leave the 27 blocks
+    # around their block in the drift (the per-wavefront rank fallback)
+    "far32": dict(c=2, n_part=32, n_mesh=32, box=16.0, n_steps=1, galaxies=2e4),
+    "far32_mesh2": dict(c=2, n_part=32, n_mesh=64, box=16.0, n_steps=1, galaxies=2e4),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}
