@@ -530,13 +530,15 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
   flush_window<T>(m.o, L, acc, 1, MPtrs<T>{{rho}});
 }
 
-// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart.
+// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart; v
+// of slot a is read at slot src[a] (the order the cotangents were left in).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ d,
                                                           const T* __restrict__ v, T coef,
                                                           long long P, int lp, Grid<T> g,
                                                           Layout L, Items it, T* __restrict__ out,
-                                                          long long M) {
+                                                          long long M,
+                                                          const unsigned* __restrict__ src) {
   __shared__ double acc[3 * kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     ok[k] = item_slot(m, it, k, lp, a, idx[k]);
     if (!ok[k]) continue;
     pk::load3(d, P, a, dsp[k]);
-    pk::load3(v, P, a, vv[k]);
+    pk::load3(v, P, static_cast<long long>(src[a]), vv[k]);
   }
   zero_window(acc, 3);
   __syncthreads();
@@ -646,12 +648,17 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
 }
 
 // Position cotangent of one force evaluation (see pk::k_force_adjoint) with
-// g (three meshes) and rho_bar read from one four-field window.
+// g (three meshes) and rho_bar read from one four-field window.  The incoming
+// cotangents of slot a are read at slot src[a] of the order they were left
+// in (the next order, or the data order), the updated ones are written to
+// slot a (dbar_out, pbar_out): the move between orders costs no pass of its
+// own.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
-    const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
+    const T* __restrict__ d, const T* __restrict__ pbar, const T* __restrict__ dbar, T coef,
     const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
-    int lp, Grid<T> gm, Layout L, Items it) {
+    int lp, Grid<T> gm, Layout L, Items it, const unsigned* __restrict__ src,
+    T* __restrict__ dbar_out, T* __restrict__ pbar_out) {
   __shared__ T lds[4 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
@@ -663,9 +670,10 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
   for (int k = 0; k < kPer; ++k) {
     ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
     if (!ok[k]) continue;
+    const long long j = src[a[k]];
     pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(pbar, P, a[k], pb[k]);
-    pk::load3(dbar, P, a[k], db[k]);
+    pk::load3(pbar, P, j, pb[k]);
+    pk::load3(dbar, P, j, db[k]);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M, rho_bar}}, 4, lds);
   __syncthreads();
@@ -685,8 +693,8 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       db[k][q] += xb[q] * gm.inv_cell;
-      dbar[q * P + a[k]] = db[k][q];
-      if (drift != T(0)) pbar[q * P + a[k]] = pb[k][q] + drift * db[k][q];
+      dbar_out[q * P + a[k]] = db[k][q];
+      pbar_out[q * P + a[k]] = pb[k][q] + drift * db[k][q];
     }
   }
 }

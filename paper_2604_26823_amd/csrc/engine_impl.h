@@ -784,15 +784,13 @@ class Engine final : public EngineBase {
   // Reverse sweep from the seed in seed_; out = J^T seed + beta_aux aux.
   void adjoint(T* out, const T* aux, T beta_aux) {
     {
+      // cotangents in the data order; step S reads them through dest(S)
       auto sc = timer_.scope("data_adjoint", P_ * (13.0 * sizeT() + 4.0));
       bk::k_data_adjoint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
-          dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), seed_, dbar2_,
-          pbar2_);
+          dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), seed_, dbar_,
+          pbar_);
       IC_LAUNCHED();
     }
-    std::swap(dbar_, dbar2_);
-    std::swap(pbar_, pbar2_);
-    cotangents_back(dest(S_));
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
     const double sc_rho = -1.0 / ((double)P_ / (double)M_ * (double)M_);
     for (int n = S_; n >= 0; --n) {
@@ -803,9 +801,9 @@ class Engine final : public EngineBase {
       const bk::Items it = items(mesh_order(n), ids(n));
       fill(gbar_, T(0), 3 * M_);
       {
-        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 4.0) + 6.0 * M_ * sizeT());
-        bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(dslot(n), pbar_, coef, P_, lp_,
-                                                             gmesh(), Lm_, it, gbar_, M_);
+        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
+        bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n));
         IC_LAUNCHED();
       }
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
@@ -816,14 +814,19 @@ class Engine final : public EngineBase {
       chain_gather(1, ins, sp, 3, rhobar_, nullptr, T(0));
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       {
-        auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 4.0) + 4.0 * M_ * sizeT());
+        // reads the cotangents of order n + 1 (the data order for n = S)
+        // through dest(n), writes them in order n
+        auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 8.0) + 4.0 * M_ * sizeT());
         bk::k_force_adjoint_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it);
+            dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it,
+            dest(n), dbar2_, pbar2_);
         IC_LAUNCHED();
       }
-      // To order n - 1 (the lattice order after n = 0).
-      cotangents_back(dest(n - 1));
+      std::swap(dbar_, dbar2_);
+      std::swap(pbar_, pbar2_);
     }
+    // order 0 to the lattice order of the 2LPT adjoint
+    cotangents_back(dest(-1));
     // 2LPT and whitening adjoint.
     const double inv = 1.0 / (double)P_;
     const double a2E = prob_.a_init * prob_.a_init * co_.E_init;
