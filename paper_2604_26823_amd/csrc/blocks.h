@@ -531,14 +531,16 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
 }
 
 // g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart; v
-// of slot a is read at slot src[a] (the order the cotangents were left in).
+// of slot a is read at slot src[a] (the order the cotangents were left in)
+// and written to v_out[a], in this order, for the force adjoint.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ d,
                                                           const T* __restrict__ v, T coef,
                                                           long long P, int lp, Grid<T> g,
                                                           Layout L, Items it, T* __restrict__ out,
                                                           long long M,
-                                                          const unsigned* __restrict__ src) {
+                                                          const unsigned* __restrict__ src,
+                                                          T* __restrict__ v_out) {
   __shared__ double acc[3 * kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
@@ -552,6 +554,8 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     if (!ok[k]) continue;
     pk::load3(d, P, a, dsp[k]);
     pk::load3(v, P, static_cast<long long>(src[a]), vv[k]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v_out[q * P + a] = vv[k][q];
   }
   zero_window(acc, 3);
   __syncthreads();
@@ -648,17 +652,17 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
 }
 
 // Position cotangent of one force evaluation (see pk::k_force_adjoint) with
-// g (three meshes) and rho_bar read from one four-field window.  The incoming
-// cotangents of slot a are read at slot src[a] of the order they were left
-// in (the next order, or the data order), the updated ones are written to
-// slot a (dbar_out, pbar_out): the move between orders costs no pass of its
-// own.
+// g (three meshes) and rho_bar read from one four-field window.  p_bar is
+// already in this order (written by the cotangent paint) and is updated in
+// place; d_bar of slot a is read at slot src[a] of the order it was left in
+// (the next order, or the data order) and the update goes to dbar_out[a], so
+// the move between orders costs no pass of its own.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
-    const T* __restrict__ d, const T* __restrict__ pbar, const T* __restrict__ dbar, T coef,
+    const T* __restrict__ d, T* __restrict__ pbar, const T* __restrict__ dbar, T coef,
     const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
     int lp, Grid<T> gm, Layout L, Items it, const unsigned* __restrict__ src,
-    T* __restrict__ dbar_out, T* __restrict__ pbar_out) {
+    T* __restrict__ dbar_out) {
   __shared__ T lds[4 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
@@ -670,10 +674,9 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
   for (int k = 0; k < kPer; ++k) {
     ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
     if (!ok[k]) continue;
-    const long long j = src[a[k]];
     pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(pbar, P, j, pb[k]);
-    pk::load3(dbar, P, j, db[k]);
+    pk::load3(pbar, P, a[k], pb[k]);
+    pk::load3(dbar, P, static_cast<long long>(src[a[k]]), db[k]);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M, rho_bar}}, 4, lds);
   __syncthreads();
@@ -694,7 +697,7 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
     for (int q = 0; q < 3; ++q) {
       db[k][q] += xb[q] * gm.inv_cell;
       dbar_out[q * P + a[k]] = db[k][q];
-      pbar_out[q * P + a[k]] = pb[k][q] + drift * db[k][q];
+      if (drift != T(0)) pbar[q * P + a[k]] = pb[k][q] + drift * db[k][q];
     }
   }
 }

@@ -801,9 +801,9 @@ class Engine final : public EngineBase {
       const bk::Items it = items(mesh_order(n), ids(n));
       fill(gbar_, T(0), 3 * M_);
       {
-        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
+        auto sc = timer_.scope("cic_paint_vec", P_ * (9.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
         bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n));
+            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), pbar2_);
         IC_LAUNCHED();
       }
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
@@ -814,12 +814,12 @@ class Engine final : public EngineBase {
       chain_gather(1, ins, sp, 3, rhobar_, nullptr, T(0));
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       {
-        // reads the cotangents of order n + 1 (the data order for n = S)
-        // through dest(n), writes them in order n
+        // p_bar in order n (pbar2_, from the paint); d_bar read from order
+        // n + 1 (the data order for n = S) through dest(n), written in order n
         auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 8.0) + 4.0 * M_ * sizeT());
         bk::k_force_adjoint_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it,
-            dest(n), dbar2_, pbar2_);
+            dslot(n), pbar2_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it,
+            dest(n), dbar2_);
         IC_LAUNCHED();
       }
       std::swap(dbar_, dbar2_);
