@@ -11,12 +11,17 @@ synthetic configurations:
    force F = -grad lap^-1 delta_m on the mesh and CIC readout           (item 2)
 4. RSD at a_final: shift c (p . d) d with d the line of sight from the
    observer (radial) or the z axis (plane parallel); c = 1/(a^2 E)       (item 3)
-5. CIC of the shifted particles on the data grid -> delta_s; linear bias and
-   response, lambda = Nbar R (1 + b delta_s)                            (items 4-5)
-6. Loss L = 1/2 sum_M (N - lambda)^2 / sigma^2 + 1/2 w_prior sum s^2 with
-   sigma^2 = Nbar R and mask M = [R >= r_min].  The paper's own likelihood is
-   Poisson (section 2.2.2); the Gaussian chi^2 with a white-noise prior is
-   the objective of the reconstructions this library benchmarks.
+5. CIC of the shifted particles on the data grid -> delta_s; bias and
+   response (items 4-5): linear, lambda = Nbar R (1 + b delta_s), or the
+   paper's power law times a sigmoid (item 4, eq. of the galaxy bias),
+   lambda = Nbar R u^alpha sigmoid(K (delta_s - delta_th)), u = 1 + delta_s
+   floored at 1e-6 (the paper leaves lambda = 0 in empty cells, where
+   log lambda diverges; below the floor u is constant).
+6. Loss L = 1/2 D + 1/2 w_prior sum s^2 over the mask M = [R >= r_min], with
+   the data term D = sum_M (N - lambda)^2 / sigma^2, sigma^2 = Nbar R (the
+   Gaussian chi^2 of the benchmarked reconstructions), or D = -2 log L_P with
+   the paper's Poisson log-likelihood (section 2.2.2), log L_P =
+   sum_M (-lambda + N log lambda - log N!).
 
 Particles carry a displacement d from their lattice point q_n = n dq and a
 momentum p = a^3 E dx/da, stored as (3, N_p^3) arrays in C order of n.
@@ -49,6 +54,10 @@ class Problem:
     nbar: float = 1.0
     r_min: float = 1e-3
     prior_weight: float = 1.0
+    loss: str = "gauss"            # 'gauss' (linear bias, chi^2) | 'poisson' (paper's model)
+    bias_alpha: float = 0.7        # power-law index alpha (section 2.2.1, item 4)
+    bias_delta_th: float = 1.2     # sigmoid threshold delta_th
+    bias_k: float = 3.0            # sigmoid steepness K
 
 
 class Model:
@@ -170,12 +179,23 @@ class Model:
         n = self.p.n_part
         return cic.paint(self.q + ds, n, self.dq) - 1.0
 
+    U_FLOOR = 1e-6   # floor of 1 + delta_s in the power-law bias
+
     def observe(self, delta_s, response):
-        """lambda = Nbar R (1 + b delta_s)."""
+        """lambda = Nbar R (1 + b delta_s), or Nbar R u^alpha sigmoid(K (delta_s - delta_th))."""
+        if self.p.loss == "poisson":
+            u = np.maximum(1.0 + delta_s, self.U_FLOOR)
+            sig = 1.0 / (1.0 + np.exp(-self.p.bias_k * (delta_s - self.p.bias_delta_th)))
+            return self.p.nbar * response * u ** self.p.bias_alpha * sig
         return self.p.nbar * response * (1.0 + self.p.bias * delta_s)
 
     def chi2(self, lam, counts, response):
+        """Data term D: Gaussian chi^2, or -2 log L_P of the Poisson model."""
         m = response >= self.p.r_min
+        if self.p.loss == "poisson":
+            from scipy.special import gammaln
+            n = counts[m].astype(np.float64)
+            return float(2.0 * np.sum(lam[m] - n * np.log(lam[m]) + gammaln(n + 1.0)))
         var = self.p.nbar * response[m]
         return float(np.sum((counts[m] - lam[m]) ** 2 / var))
 
@@ -203,10 +223,20 @@ class Model:
         return self.data_density(self.rsd(dS, pS))
 
     # ---------------------------------------------------------------- adjoint
-    def loss_seed(self, lam, counts, response):
-        """dL/d delta_s = M b Nbar R (lambda - N) / sigma^2."""
+    def loss_seed(self, lam, counts, response, delta_s=None):
+        """dL/d delta_s = 1/2 dD/d delta_s: M b Nbar R (lambda - N) / sigma^2 (Gaussian), or
+        M (1 - N / lambda) dlambda/d delta_s (Poisson, delta_s needed)."""
         m = response >= self.p.r_min
         out = np.zeros_like(lam)
+        if self.p.loss == "poisson":
+            d = delta_s[m]
+            a, k = self.p.bias_alpha, self.p.bias_k
+            u = np.maximum(1.0 + d, self.U_FLOOR)
+            sig = 1.0 / (1.0 + np.exp(-k * (d - self.p.bias_delta_th)))
+            du = np.where(1.0 + d > self.U_FLOOR, a * u ** (a - 1.0), 0.0)
+            dlam = self.p.nbar * response[m] * (du * sig + u ** a * k * sig * (1.0 - sig))
+            out[m] = (1.0 - counts[m] / lam[m]) * dlam
+            return out
         var = self.p.nbar * response[m]
         out[m] = self.p.bias * self.p.nbar * response[m] * (lam[m] - counts[m]) / var
         return out
@@ -281,7 +311,7 @@ class Model:
         """(L, grad L, state)."""
         s = np.asarray(s, dtype=np.float64)
         L, st = self.loss(s, counts, response, return_state=True)
-        seed = self.loss_seed(st["lam"], counts, response)
+        seed = self.loss_seed(st["lam"], counts, response, st["delta_s"])
         grad = self.vjp_state(st, seed) + self.p.prior_weight * s
         return L, grad, st
 
