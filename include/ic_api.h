@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IC_ABI_VERSION 2
+#define IC_ABI_VERSION 3
 
 #define IC_OK 0
 #define IC_ERR_INVALID_ARG (-1)
@@ -76,6 +76,16 @@ extern "C" {
 #define IC_DEFAULT_A_INIT 0.1
 #define IC_DEFAULT_EPS_MAX 1.0
 
+/* loss_kind */
+#define IC_LOSS_GAUSS 0    /* linear bias, masked Gaussian chi^2 (the benchmarked objective) */
+#define IC_LOSS_POISSON 1  /* the paper's bias and Poisson likelihood (sections 2.2.1-2.2.2) */
+
+/* The paper's galaxy bias (section 2.2.1, item 4, the power law times a
+ * sigmoid): lambda = nbar R (1 + delta)^alpha sigmoid(K (delta - delta_th)). */
+#define IC_DEFAULT_BIAS_ALPHA 0.7
+#define IC_DEFAULT_BIAS_DELTA_TH 1.2
+#define IC_DEFAULT_BIAS_K 3.0
+
 /* The reconstruction problem (sections 2.2-2.3).  Lengths in Mpc/h. */
 typedef struct ic_problem {
   int32_t n_part;        /* particles per side = white-noise and data grid side */
@@ -103,11 +113,20 @@ typedef struct ic_problem {
                             0: keep every step's state */
   double rom_kmin;       /* smallest matched |k| (0.1 h/Mpc) */
   uint64_t seed;         /* key of the counter-based generator */
+  double bias_alpha;     /* IC_LOSS_POISSON: power-law index alpha (0.7) */
+  double bias_delta_th;  /* IC_LOSS_POISSON: sigmoid threshold delta_th (1.2) */
+  double bias_k;         /* IC_LOSS_POISSON: sigmoid steepness K (3.0) */
+  int32_t loss_kind;     /* IC_LOSS_GAUSS or IC_LOSS_POISSON.  Poisson: lambda = nbar R
+                            u^alpha sigmoid(K (delta_s - delta_th)) with u = 1 + delta_s
+                            floored at 1e-6 (constant below the floor), data term
+                            D = -2 sum_M (N log lambda - lambda - log N!); bias unused */
 } ic_problem;
 
 typedef struct ic_loss_terms {
   double loss;           /* 1/2 chi2 + 1/2 prior_weight |s|^2 */
-  double chi2;           /* sum over masked cells of (N - lambda)^2 / (nbar R) */
+  double chi2;           /* data term D over the masked cells: sum (N - lambda)^2 / (nbar R)
+                            (IC_LOSS_GAUSS) or -2 log L of the Poisson model (IC_LOSS_POISSON);
+                            loss = 1/2 D + 1/2 prior_weight |s|^2 */
   double prior;          /* |s|^2 */
   int64_t n_masked;      /* cells with R >= r_min */
 } ic_loss_terms;

@@ -44,6 +44,8 @@ class IcProblem(ctypes.Structure):
         ("rom_nbins", ctypes.c_int32), ("tape_forces", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32),
         ("rom_kmin", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("bias_alpha", ctypes.c_double), ("bias_delta_th", ctypes.c_double),
+        ("bias_k", ctypes.c_double), ("loss_kind", ctypes.c_int32),
     ]
 
 

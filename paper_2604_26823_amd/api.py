@@ -15,7 +15,7 @@ from ._lib import IcLbfgsInfo, IcLossTerms, IcProblem, IcRomInfo
 PROBLEM_KEYS = ["n_part", "n_mesh", "n_steps", "box", "a_init", "a_final", "omega_m", "h",
                 "n_s", "sigma8", "bias", "nbar", "r_min", "prior_weight", "lbfgs_m",
                 "max_trials", "eps_max", "armijo_c1", "s_th", "rom_nbins", "tape_forces", "ckpt_every",
-                "rom_kmin", "seed"]
+                "rom_kmin", "seed", "bias_alpha", "bias_delta_th", "bias_k"]
 
 
 def make_problem(cfg):
@@ -28,6 +28,8 @@ def make_problem(cfg):
             setattr(p, k, type(getattr(p, k))(cfg[k]))
     if "rsd" in cfg:
         p.rsd_mode = _lib.IC_RSD[cfg["rsd"]]
+    if "loss" in cfg:
+        p.loss_kind = {"gauss": 0, "poisson": 1}[cfg["loss"]]
     if "observer" in cfg:
         for a in range(3):
             p.observer[a] = float(cfg["observer"][a])

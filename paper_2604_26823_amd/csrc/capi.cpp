@@ -72,6 +72,10 @@ void validate_problem(const ic_problem& p) {
   if (!(p.s_th > 0)) bad(IC_ERR_INVALID_ARG, "s_th must be positive");
   if (p.rom_nbins < 1 || p.rom_nbins > 127) bad(IC_ERR_INVALID_ARG, "rom_nbins must be in [1, 127]");
   if (p.ckpt_every < 0) bad(IC_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  if (p.loss_kind != IC_LOSS_GAUSS && p.loss_kind != IC_LOSS_POISSON)
+    bad(IC_ERR_INVALID_ARG, "unknown loss_kind");
+  if (p.loss_kind == IC_LOSS_POISSON && !(p.bias_alpha > 0 && p.bias_k > 0))
+    bad(IC_ERR_INVALID_ARG, "bias_alpha and bias_k must be positive");
 }
 
 size_t workspace_bytes(const ic_problem& p, int precision) {
@@ -119,6 +123,10 @@ void ic_problem_defaults(ic_problem* p) {
   p->rom_nbins = IC_DEFAULT_ROM_NBINS;
   p->tape_forces = 1;
   p->ckpt_every = 0;
+  p->loss_kind = IC_LOSS_GAUSS;
+  p->bias_alpha = IC_DEFAULT_BIAS_ALPHA;
+  p->bias_delta_th = IC_DEFAULT_BIAS_DELTA_TH;
+  p->bias_k = IC_DEFAULT_BIAS_K;
   p->rom_kmin = IC_DEFAULT_ROM_KMIN;
   p->seed = 0;
 }

@@ -765,10 +765,17 @@ class Engine final : public EngineBase {
     const unsigned g = grid_for(P_, fk::kRedThreads, kRedBlocks);
     {
       auto sc = timer_.scope("loss", 5.0 * P_ * sizeT());
+      fk::Obs<T> o;
+      o.poisson = prob_.loss_kind == IC_LOSS_POISSON ? 1 : 0;
+      o.nbar = static_cast<T>(prob_.nbar);
+      o.bias = static_cast<T>(prob_.bias);
+      o.r_min = static_cast<T>(prob_.r_min);
+      o.alpha = static_cast<T>(prob_.bias_alpha);
+      o.delta_th = static_cast<T>(prob_.bias_delta_th);
+      o.k = static_cast<T>(prob_.bias_k);
       fk::k_loss<T><<<g, fk::kRedThreads, 0, st_>>>(
-          rhod_, want_loss ? counts_ : nullptr, resp_, s, static_cast<T>(prob_.nbar),
-          static_cast<T>(prob_.bias), static_cast<T>(prob_.r_min), want_loss ? seed_ : nullptr,
-          delta, lambda, part_, P_);
+          rhod_, want_loss ? counts_ : nullptr, resp_, s, o, want_loss ? seed_ : nullptr, delta,
+          lambda, part_, P_);
       IC_LAUNCHED();
     }
     if (!t) return;

@@ -83,18 +83,32 @@ __global__ void k_lpt_assemble(T* __restrict__ d, T* __restrict__ p, T cd1, T cd
   }
 }
 
+// Observation model of the data grid (section 2.2.1, items 4-5).
+template <typename T>
+struct Obs {
+  int poisson;           // 0: linear bias, Gaussian chi^2; 1: the paper's model
+  T nbar, bias, r_min;   // bias: linear b (Gaussian model only)
+  T alpha, delta_th, k;  // power-law index, sigmoid threshold and steepness
+};
+
+// Floor of 1 + delta in the power-law bias: the paper's rate vanishes in
+// empty cells, where log lambda diverges; below the floor u is constant.
+constexpr double kUFloor = 1e-6;
+
 // Observation model and loss on the data grid.  delta = rho - 1 (one particle
-// per data cell on average); lambda = nbar R (1 + b delta) when R is given;
-// with counts also given, masked cells (R >= r_min) add (N - lambda)^2 /
-// (nbar R) to chi^2 and get the adjoint seed b nbar R (lambda - N) / (nbar R).
-// Per-block FP64 partial sums of chi^2, |s|^2 and the masked-cell count go to
-// part[3 * block + k].
+// per data cell on average).  When R is given: lambda = nbar R (1 + b delta)
+// (Gaussian model) or lambda = nbar R u^alpha sigmoid(K (delta - delta_th)),
+// u = max(1 + delta, kUFloor) (Poisson model).  With counts also given, each
+// masked cell (R >= r_min) adds to the data term D either (N - lambda)^2 /
+// (nbar R), with adjoint seed 1/2 dD/d delta = b nbar R (lambda - N) /
+// (nbar R), or -2 (N log lambda - lambda - log N!) (section 2.2.2), with seed
+// (1 - N / lambda) dlambda/d delta.  Per-block FP64 partial sums of D, |s|^2
+// and the masked-cell count go to part[3 * block + k].
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_loss(
     const T* __restrict__ rho, const int* __restrict__ counts, const T* __restrict__ R,
-    const T* __restrict__ s, T nbar, T bias, T r_min, T* __restrict__ seed,
-    T* __restrict__ delta_out, T* __restrict__ lambda_out, double* __restrict__ part,
-    long long n) {
+    const T* __restrict__ s, Obs<T> o, T* __restrict__ seed, T* __restrict__ delta_out,
+    T* __restrict__ lambda_out, double* __restrict__ part, long long n) {
   __shared__ double sh[kRedThreads / 64];
   double chi = 0, ss = 0, cnt = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -104,14 +118,31 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
     if (delta_out) delta_out[i] = delta;
     if (R) {
       const T r = R[i];
-      const T lam = nbar * r * (T(1) + bias * delta);
+      T lam, dlam = T(0);
+      if (o.poisson) {
+        const T u = T(1) + delta > T(kUFloor) ? T(1) + delta : T(kUFloor);
+        const T sig = T(1) / (T(1) + exp(-o.k * (delta - o.delta_th)));
+        const T ua = pow(u, o.alpha);
+        lam = o.nbar * r * ua * sig;
+        const T du = T(1) + delta > T(kUFloor) ? o.alpha * ua / u : T(0);
+        dlam = o.nbar * r * (du * sig + ua * o.k * sig * (T(1) - sig));
+      } else {
+        lam = o.nbar * r * (T(1) + o.bias * delta);
+      }
       if (lambda_out) lambda_out[i] = lam;
-      if (counts && r >= r_min) {
-        const T var = nbar * r;
-        const double res = static_cast<double>(counts[i]) - static_cast<double>(lam);
-        chi += res * res / static_cast<double>(var);
+      if (counts && r >= o.r_min) {
+        const int nc = counts[i];
+        if (o.poisson) {
+          const double l = static_cast<double>(lam), nn = static_cast<double>(nc);
+          chi += 2.0 * (l - nn * log(l) + lgamma(nn + 1.0));
+          sd = (T(1) - static_cast<T>(nc) / lam) * dlam;
+        } else {
+          const T var = o.nbar * r;
+          const double res = static_cast<double>(nc) - static_cast<double>(lam);
+          chi += res * res / static_cast<double>(var);
+          sd = o.bias * o.nbar * r * (lam - static_cast<T>(nc)) / var;
+        }
         cnt += 1.0;
-        sd = bias * nbar * r * (lam - static_cast<T>(counts[i])) / var;
       }
     }
     if (seed) seed[i] = sd;

@@ -34,6 +34,11 @@ CASES = {
     # around their block in the drift (the per-wavefront rank fallback)
     "far32": dict(c=2, n_part=32, n_mesh=32, box=16.0, n_steps=1, galaxies=2e4),
     "far32_mesh2": dict(c=2, n_part=32, n_mesh=64, box=16.0, n_steps=1, galaxies=2e4),
+    # the paper's observation model: power-law x sigmoid bias, Poisson likelihood;
+    # with the white-noise prior, and likelihood only (prior weight 0)
+    "poisson_c1": dict(c=1, loss="poisson"),
+    "poisson_radial32": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5, galaxies=2e4,
+                             loss="poisson", prior_weight=0.0),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}

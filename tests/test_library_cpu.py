@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.ic_abi_version() == 2
+    assert lib.ic_abi_version() == 3
     p = _lib.IcProblem()
     lib.ic_problem_defaults(ctypes.byref(p))
     assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
@@ -74,6 +74,14 @@ def test_workspace_sizes_and_validation(lib):
     assert rc == -1
     rc, _ = _size(lib, inputs.config(1, ckpt_every=-1))
     assert rc == -1
+    p = api.make_problem(inputs.config(1))
+    assert p.loss_kind == 0 and (p.bias_alpha, p.bias_delta_th, p.bias_k) == (0.7, 1.2, 3.0)
+    p.loss_kind = 2
+    size = ctypes.c_size_t()
+    assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
+    p.loss_kind = 1
+    p.bias_k = 0.0
+    assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
 
 
 def test_checkpoints_and_recomputed_forces_shrink_the_workspace(lib):
