@@ -4,9 +4,9 @@
 // of its CIC base cell (the wrapped floor cell of its position), so all eight
 // corners of its stencil fall inside that block extended by one cell on the
 // upper side: a fixed 9^3-cell window.  After each drift the particles are
-// counting-sorted by block (per-block counts with wavefront-aggregated
+// counting-sorted by block (per-block counts with wavefront- or workgroup-aggregated
 // atomics, an exclusive scan, a scatter of the state into block order), and
-// every paint and readout then runs over work items of at most 512 particles
+// every paint and readout then runs over work items of at most 1024 particles
 // of one block, with the block's window in LDS:
 //   * paints accumulate in FP64 LDS windows (ds_add_f64; the FP32 LDS atomic
 //     add of gfx950 runs at a small fraction of the FP64 rate) and flush each
@@ -23,8 +23,10 @@
 // of the global atomics, which is unordered anyway.
 //
 // Slot a of a sorted state holds the particle with Lagrangian index ids[a];
-// dest[a] gives its slot in the next order, so cotangents move back from one
-// order to the previous one by a gather through dest.
+// dest[a] gives its slot in the next order.  The adjoint kernels of order n
+// read the cotangents left in order n + 1 through dest and write them in
+// order n, so no pass of its own moves them between orders (one gather takes
+// order 0 back to the lattice order).
 #pragma once
 
 #include "particles.h"

@@ -747,8 +747,8 @@ class Engine final : public EngineBase {
     return bk::MPtrs<T>{{d, d + P_, d + 2 * P_, p, p + P_, p + 2 * P_}};
   }
 
-  // Cotangents (dbar_, pbar_) of one order brought back to the previous one
-  // through dest_slots (buffers swapped with dbar2_, pbar2_).
+  // Cotangents (dbar_, pbar_) of order 0 brought to the lattice order through
+  // dest_slots (buffers swapped with dbar2_, pbar2_).
   void cotangents_back(const unsigned* dest_slots) {
     {
       auto sc = timer_.scope("sort_gather_back", P_ * (12.0 * sizeT() + 4.0));
