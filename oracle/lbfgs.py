@@ -32,10 +32,13 @@ class LineSearchError(RuntimeError):
 
 class ProjectedLBFGS:
     def __init__(self, m=10, eps_max=1.0, c1=1e-4, max_trials=30, s_th=10.0,
-                 seed=0, curvature_eps=1e-10):
+                 seed=0, curvature_eps=1e-10, project_steps=True):
         self.m, self.eps_max, self.c1 = m, eps_max, c1
         self.max_trials, self.s_th, self.seed = max_trials, s_th, seed
         self.curvature_eps = curvature_eps
+        # False: plain L-BFGS trial points s + eps p (the ablation baseline of
+        # appendix B, table 1) instead of P(s + eps p)
+        self.project_steps = project_steps
         self.S, self.Y = [], []
 
     def reset(self):
@@ -66,7 +69,10 @@ class ProjectedLBFGS:
         eps = self.eps_max
         for k in range(self.max_trials):
             trial = first_trial + k
-            s_t, resets = project(s + eps * p, self.s_th, self.seed, iteration, trial)
+            if self.project_steps:
+                s_t, resets = project(s + eps * p, self.s_th, self.seed, iteration, trial)
+            else:
+                s_t, resets = s + eps * p, 0
             L_t, g_t = fun(s_t)
             g_t = np.asarray(g_t, dtype=np.float64).reshape(-1)
             s_t = s_t.reshape(-1)

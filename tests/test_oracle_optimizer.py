@@ -257,3 +257,31 @@ def test_line_search_restarts_with_steepest_descent():
     s2, g2, L2, info = opt.step(s, g, L, fun, 0)
     assert info["restarted"] and L2 < L
     assert info["evaluations"] == info["trials"]  # 5 failed trials, then the -g search
+
+
+def test_plain_lbfgs_reaches_the_minimiser_of_a_quadratic():
+    """Without projected steps the method is plain backtracking L-BFGS: on a
+    strictly convex quadratic 1/2 x^T A x - b^T x it reaches the solution of
+    A x = b (an independent linear solve)."""
+    from oracle import lbfgs
+    rng = np.random.default_rng(31)
+    n = 60
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 30.0, n)) @ Q.T
+    b = rng.standard_normal(n)
+
+    def fun(x):
+        x = x.reshape(-1)
+        return 0.5 * x @ A @ x - b @ x, A @ x - b
+
+    opt = lbfgs.ProjectedLBFGS(project_steps=False)
+    x = np.zeros(n)
+    L, g = fun(x)
+    for it in range(200):
+        if np.linalg.norm(g) < 1e-6:   # |x - x*| <= |g| / lambda_min = |g|
+            break
+        x, g, L, info = opt.step(x, g, L, fun, it)
+        assert info["resets"] == 0
+    assert np.linalg.norm(g) < 1e-6
+    ref = np.linalg.solve(A, b)
+    assert np.max(np.abs(x - ref)) <= 1e-6
