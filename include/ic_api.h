@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IC_ABI_VERSION 3
+#define IC_ABI_VERSION 4
 
 #define IC_OK 0
 #define IC_ERR_INVALID_ARG (-1)
@@ -120,6 +120,9 @@ typedef struct ic_problem {
                             u^alpha sigmoid(K (delta_s - delta_th)) with u = 1 + delta_s
                             floored at 1e-6 (constant below the floor), data term
                             D = -2 sum_M (N log lambda - lambda - log N!); bias unused */
+  int32_t project_steps; /* 1: trial points P(s + eps p) (the method, section 2.3.1);
+                            0: plain L-BFGS trial points s + eps p (the ablation's
+                            baseline, appendix B) */
 } ic_problem;
 
 typedef struct ic_loss_terms {

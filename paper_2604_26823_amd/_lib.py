@@ -46,6 +46,7 @@ class IcProblem(ctypes.Structure):
         ("rom_kmin", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("bias_alpha", ctypes.c_double), ("bias_delta_th", ctypes.c_double),
         ("bias_k", ctypes.c_double), ("loss_kind", ctypes.c_int32),
+        ("project_steps", ctypes.c_int32),
     ]
 
 

@@ -127,6 +127,7 @@ void ic_problem_defaults(ic_problem* p) {
   p->bias_alpha = IC_DEFAULT_BIAS_ALPHA;
   p->bias_delta_th = IC_DEFAULT_BIAS_DELTA_TH;
   p->bias_k = IC_DEFAULT_BIAS_K;
+  p->project_steps = 1;
   p->rom_kmin = IC_DEFAULT_ROM_KMIN;
   p->seed = 0;
 }

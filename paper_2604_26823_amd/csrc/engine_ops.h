@@ -176,7 +176,8 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
   // Backtracking along the projection arc: accept s' = P(s + eps p) when
   // g.(s' - s) < 0, L(s') < L and L(s') <= L + c1 g.(s' - s).  A quasi-Newton direction
   // whose search fails is replaced once by steepest descent (history reset),
-  // with trial numbers continuing after max_trials.
+  // with trial numbers continuing after max_trials.  Without projected steps
+  // (project_steps = 0) s' = s + eps p: plain backtracking L-BFGS.
   double eps = 0;
   bool accepted = false;
   ic_loss_terms t{};
@@ -193,7 +194,8 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
     for (int k = 0; k < prob_.max_trials; ++k) {
       const int trial = attempt * prob_.max_trials + k;
       axpy(s, dir_, eps, strial_, P_);
-      inf.resets = project(strial_, strial_, (uint64_t)trial, (uint64_t)it);
+      inf.resets = prob_.project_steps ? project(strial_, strial_, (uint64_t)trial, (uint64_t)it)
+                                       : 0;
       eval(strial_, gtrial_, &t);
       inf.evaluations++;
       used = k + 1;

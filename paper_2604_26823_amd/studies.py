@@ -16,6 +16,18 @@
       projected L-BFGS iterations with rank-order matching every 20.  FP64:
       one evaluation at the same start, compared with FP32.
 
+  python -m paper_2604_26823_amd.studies ablation [--iterations 200] [--out F]
+      The optimiser ablation of appendix B (table 1) on synthetic data of
+      the 128^3, 512 Mpc/h radial-selection configuration: the method
+      (projected steps, eps_max = 1, rank-order matching every 20) against
+      plain L-BFGS (trial points s + eps p, no matching) with eps_max = 1,
+      0.1, 0.01, 0.001.  Per run: the loss every 10 iterations, the loss of
+      the homogeneous start s = 0 for reference, moments of the final white
+      noise, its cross-correlation coefficient r_c(k) with the truth over the
+      box, and the correlation with the truth of both fields smoothed over 4
+      cells, on the cells under the mask; the losses of s = 0 and of the
+      truth for reference.
+
 Every output line is one JSON record (also appended to --out)."""
 import argparse
 import json
@@ -189,11 +201,117 @@ def scale(a):
     ctx.close()
 
 
+def _white_noise_stats(x):
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    m, sd = float(x.mean()), float(x.std())
+    z = (x - m) / sd
+    return dict(mean=m, std=sd, max_abs=float(np.abs(x).max()),
+                excess_kurtosis=float(np.mean(z ** 4) - 3.0),
+                frac_above_4=float(np.mean(np.abs(x) > 4.0)))
+
+
+def _smooth(x, cells):
+    """Gaussian smoothing (sigma in cells) by a host FFT: the large scales the
+    data constrain, without the small-scale white noise they leave free."""
+    n = x.shape[0]
+    j = np.fft.fftfreq(n, 1.0 / n)
+    jz = np.arange(n // 2 + 1)
+    k2 = (2 * np.pi / n) ** 2 * (j[:, None, None] ** 2 + j[None, :, None] ** 2
+                                 + jz[None, None, :] ** 2)
+    return np.fft.irfftn(np.fft.rfftn(x) * np.exp(-0.5 * k2 * cells ** 2), s=x.shape)
+
+
+def _cross_correlation(a, b, box, nbins=10):
+    """r_c(k) = P_ab / sqrt(P_aa P_bb) in linear k bins up to the Nyquist
+    frequency (host FFT of two fields; a diagnostic, not part of the path)."""
+    n = a.shape[0]
+    fa, fb = np.fft.rfftn(a), np.fft.rfftn(b)
+    kf = 2.0 * np.pi / box
+    j = np.fft.fftfreq(n, 1.0 / n)
+    jz = np.arange(n // 2 + 1)
+    k = kf * np.sqrt(j[:, None, None] ** 2 + j[None, :, None] ** 2 + jz[None, None, :] ** 2)
+    w = np.full(fa.shape, 2.0)
+    w[..., 0] = 1.0
+    w[..., -1] = 1.0
+    edges = np.linspace(kf, np.pi * n / box, nbins + 1)
+    out = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (k >= lo) & (k < hi)
+        pab = np.sum(w[m] * (fa[m] * np.conj(fb[m])).real)
+        paa = np.sum(w[m] * np.abs(fa[m]) ** 2)
+        pbb = np.sum(w[m] * np.abs(fb[m]) ** 2)
+        out.append([0.5 * (lo + hi), float(pab / np.sqrt(paa * pbb))])
+    return out
+
+
+def ablation(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    base = inputs.config(2)
+    R = inputs.response_field(base)
+    base["nbar"] = inputs.nbar_for(base, R)
+    sd = inputs.seeds(2)
+    s_true = inputs.white_noise(base["n_part"], sd["truth"])
+    s_start = inputs.white_noise(base["n_part"], sd["start"])
+    counts = None
+    runs = [("method", dict(project_steps=1, eps_max=1.0), True)]
+    runs += [("lbfgs_eps%g" % e, dict(project_steps=0, eps_max=e), False)
+             for e in (1.0, 0.1, 0.01, 0.001)]
+    work = "128^3, 512 Mpc/h, 10 steps, radial selection, ~1e6 galaxies"
+    for name, over, rom in runs:
+        cfg = dict(base, **over)
+        ctx = Context(cfg, "f32", "cuda:0")
+        if counts is None:
+            counts = _mock_counts(ctx, cfg, R, 2)
+            _observe(ctx, R, counts)
+            zero = torch.zeros(ctx.grid, dtype=ctx.dtype, device=ctx.device)
+            L0 = ctx.loss_and_grad(zero)[0]
+            _emit(dict(study="ablation", workload=work, run="homogeneous s = 0", loss=L0), a.out)
+            st = torch.tensor(s_true, dtype=ctx.dtype, device=ctx.device)
+            _emit(dict(study="ablation", workload=work, run="truth s_true",
+                       loss=ctx.loss_and_grad(st)[0]), a.out)
+        _observe(ctx, R, counts)
+        s = torch.tensor(s_start, dtype=ctx.dtype, device=ctx.device)
+        ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+        L, g, _ = ctx.loss_and_grad(s)
+        curve, evals, status = [[0, L]], 1, "ok"
+        t0 = time.perf_counter()
+        for it in range(a.iterations):
+            try:
+                L, info = ctx.lbfgs_step(s, g, L, it)
+            except _lib.IcError as e:
+                status = "stopped at iteration %d: %s" % (it, e)
+                break
+            evals += info["evaluations"]
+            if rom and (it + 1) % 20 == 0:
+                ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL
+                                      | _lib.IC_ROM_FOURIER, event=it + 1)
+                ctx.lbfgs_reset()
+                L, g, _ = ctx.loss_and_grad(s, g)
+                evals += 1
+            if (it + 1) % 10 == 0:
+                curve.append([it + 1, L])
+        torch.cuda.synchronize()
+        final = s.double().cpu().numpy()
+        m = R >= base["r_min"]
+        corr_m = float(np.corrcoef(_smooth(final, 4.0)[m], _smooth(s_true, 4.0)[m])[0, 1])
+        _emit(dict(study="ablation", workload=work, run=name, status=status, final_loss=L,
+                   evaluations=evals, seconds=time.perf_counter() - t0, loss_curve=curve,
+                   white_noise=_white_noise_stats(final), corr_masked=corr_m,
+                   r_c=_cross_correlation(final, s_true, base["box"])), a.out)
+        ctx.close()
+        del ctx, s, g
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
     pr = sub.add_parser("precision")
     pr.add_argument("--steps", default="")
+    ab = sub.add_parser("ablation")
+    ab.add_argument("--iterations", type=int, default=200)
     sc = sub.add_parser("scale")
     sc.add_argument("--iterations", type=int, default=50)
     sc.add_argument("--repeats", type=int, default=3)
@@ -201,10 +319,10 @@ def main():
     sc.add_argument("--tape-forces", type=int, default=0)
     sc.add_argument("--profile", action="store_true")
     sc.add_argument("--skip-f64", action="store_true")
-    for p in (pr, sc):
+    for p in (pr, sc, ab):
         p.add_argument("--out", default="")
     a = ap.parse_args()
-    (precision if a.mode == "precision" else scale)(a)
+    {"precision": precision, "scale": scale, "ablation": ablation}[a.mode](a)
 
 
 if __name__ == "__main__":

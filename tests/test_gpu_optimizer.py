@@ -141,3 +141,45 @@ def test_lbfgs_trajectory_matches_oracle(prec):
         assert np.max(rel[:4]) <= 1e-4
         assert rel[-1] <= 0.05
     assert got[-1] < got[0]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_plain_lbfgs_trajectory_matches_oracle(prec):
+    """Plain L-BFGS (project_steps = 0: trial points s + eps p, the baseline
+    of the ablation in appendix B) with eps_max = 0.1, six iterations from the
+    projected start on c1, no rank-order matching.  FP64 tracks the oracle to
+    1e-6 over all six; FP32 to 1e-4 over the first three (the path's own
+    sensitivity, see test_lbfgs_trajectory_matches_oracle)."""
+    require_gpu()
+    cfg, mdl, ctx, R, N, s0 = prepared(prec, project_steps=0, eps_max=0.1)
+    n, seed = cfg["n_part"], cfg["seed"]
+
+    def fun(x):
+        L, g, _ = mdl.loss_and_grad(x.reshape(n, n, n), N, R)
+        return L, g.reshape(-1)
+
+    s_ref, _ = projection.project(s0, 10.0, seed, 0, 0)
+    L_ref, g_ref = fun(s_ref)
+    opt = lbfgs.ProjectedLBFGS(seed=seed, eps_max=0.1, project_steps=False)
+    ref = [L_ref]
+    s_ref = s_ref.reshape(-1)
+    for it in range(6):
+        s_ref, g_ref, L_ref, info = opt.step(s_ref, g_ref, L_ref, fun, it)
+        assert info["resets"] == 0
+        ref.append(L_ref)
+
+    s = to_dev(s0, prec)
+    ctx.lbfgs_reset()
+    ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+    L, g, _ = ctx.loss_and_grad(s)
+    got = [L]
+    for it in range(6):
+        L, info = ctx.lbfgs_step(s, g, L, it)
+        assert info["resets"] == 0
+        got.append(L)
+    rel = np.abs(np.array(got) - np.array(ref)) / np.abs(np.array(ref))
+    print("plain L-BFGS trajectory rel errors:", " ".join("%.1e" % r for r in rel))
+    if prec == "f64":
+        assert np.max(rel) <= 1e-6
+    else:
+        assert np.max(rel[:4]) <= 1e-4

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.ic_abi_version() == 3
+    assert lib.ic_abi_version() == 4
     p = _lib.IcProblem()
     lib.ic_problem_defaults(ctypes.byref(p))
     assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
@@ -76,6 +76,7 @@ def test_workspace_sizes_and_validation(lib):
     assert rc == -1
     p = api.make_problem(inputs.config(1))
     assert p.loss_kind == 0 and (p.bias_alpha, p.bias_delta_th, p.bias_k) == (0.7, 1.2, 3.0)
+    assert p.project_steps == 1
     p.loss_kind = 2
     size = ctypes.c_size_t()
     assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
