@@ -228,6 +228,24 @@ int ic_lbfgs_step(ic_ctx* ctx, void* s, void* grad, double* loss, int64_t iterat
 /* Clears the L-BFGS history (after a rank-order matching event). */
 int ic_lbfgs_reset(ic_ctx* ctx);
 
+/* White-noise upsampling between the levels of the resolution schedule
+ * (section 3: the run at the coarse resolution seeds the full-resolution
+ * one).  The paper does not say how the noise moves to the finer grid; the
+ * reading here keeps the large-scale modes and draws fresh small-scale ones.
+ * s_high (device, n_part^3 of high) = inverse DFT of Z, where Z is the DFT of
+ * fresh N(0,1) noise (Philox stream 4, counter (j, 0, 4, event), j the
+ * lattice index) except on the modes whose three wave indices all lie
+ * strictly inside (-n_low/2, n_low/2), which hold the DFT of s_low (device,
+ * n_low^3 of low) times (n_part / n_low)^{3/2}; the coarse Nyquist modes are
+ * not carried.  The DFT is unnormalised, so unit-variance white noise stays
+ * unit-variance.  low must have the same precision and box and half the
+ * particle grid side of high.  Runs on high's stream (low's transform too;
+ * low's stream is restored).  Uses high's spectrum workspace; s_low is read
+ * only.  Errors (reported on high): IC_ERR_INVALID_ARG for a null or
+ * mismatched context or a null field. */
+int ic_upsample_noise(ic_ctx* high, ic_ctx* low, const void* s_low, void* s_high,
+                      uint64_t event);
+
 #ifdef __cplusplus
 }
 #endif

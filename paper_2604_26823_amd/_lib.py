@@ -23,8 +23,8 @@ IC_MULT_WHITE, IC_MULT_GRAD, IC_MULT_HESS = 1, 2, 4
 EXPORTS = [
     "ic_abi_version", "ic_problem_defaults", "ic_workspace_size", "ic_create", "ic_destroy",
     "ic_last_error", "ic_set_stream", "ic_set_observation", "ic_forward", "ic_loss_and_grad",
-    "ic_vjp", "ic_project_rankmatch", "ic_lbfgs_step", "ic_lbfgs_reset", "ic_op_rfft",
-    "ic_op_irfft", "ic_op_multiplier", "ic_op_paint", "ic_op_force", "ic_op_lpt",
+    "ic_vjp", "ic_project_rankmatch", "ic_lbfgs_step", "ic_lbfgs_reset", "ic_upsample_noise",
+    "ic_op_rfft", "ic_op_irfft", "ic_op_multiplier", "ic_op_paint", "ic_op_force", "ic_op_lpt",
     "ic_op_evolve", "ic_op_sort_desc", "ic_op_philox", "ic_debug_rom_order", "ic_timing",
     "ic_timing_only", "ic_timing_report", "ic_host_coefficients",
 ]
@@ -88,6 +88,7 @@ _SIGS = {
     "ic_lbfgs_step": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
                            ctypes.POINTER(IcLbfgsInfo)]),
     "ic_lbfgs_reset": (_I, [_P]),
+    "ic_upsample_noise": (_I, [_P, _P, _P, _P, ctypes.c_uint64]),
     "ic_op_rfft": (_I, [_P, _I, _P, _P]),
     "ic_op_irfft": (_I, [_P, _I, _P, _P]),
     "ic_op_multiplier": (_I, [_P, _I, _I, _I, _P, _P]),

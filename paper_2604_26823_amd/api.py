@@ -175,6 +175,16 @@ class Context:
     def lbfgs_reset(self):
         self._check(self.lib.ic_lbfgs_reset(self.ctx))
 
+    def upsample_from(self, low, s_low, event):
+        """White noise on this context's grid carrying the large-scale modes of
+        s_low, a field of the coarse context low (half the grid side)."""
+        self._sync_stream()
+        low._field(s_low, low.grid)
+        out = self.empty(*self.grid)
+        self._check(self.lib.ic_upsample_noise(self.ctx, low.ctx, _ptr(s_low), _ptr(out),
+                                               ctypes.c_uint64(event)))
+        return out
+
     # ---------------------------------------------------------- single stages
     def rfft(self, x, grid=_lib.IC_GRID_PART):
         self._sync_stream()

@@ -225,6 +225,15 @@ int ic_lbfgs_reset(ic_ctx* ctx) {
   return guarded(ctx, [&](ic::EngineBase& e) { e.lbfgs_reset(); });
 }
 
+int ic_upsample_noise(ic_ctx* high, ic_ctx* low, const void* s_low, void* s_high,
+                      uint64_t event) {
+  if (!low || !low->eng) return fail(high, IC_ERR_INVALID_ARG, "null coarse context");
+  if (high && low->precision != high->precision)
+    return fail(high, IC_ERR_INVALID_ARG, "contexts of different precision");
+  if (low == high) return fail(high, IC_ERR_INVALID_ARG, "coarse and fine context are the same");
+  return guarded(high, [&](ic::EngineBase& e) { e.upsample_from(*low->eng, s_low, s_high, event); });
+}
+
 static int check_grid(ic_ctx* ctx, int grid) {
   if (grid != IC_GRID_PART && grid != IC_GRID_MESH)
     return fail(ctx, IC_ERR_INVALID_ARG, "grid must be IC_GRID_PART or IC_GRID_MESH");

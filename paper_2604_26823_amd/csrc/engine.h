@@ -14,6 +14,8 @@ namespace ic {
 struct EngineBase {
   virtual ~EngineBase() = default;
   virtual void set_stream(hipStream_t s) = 0;
+  virtual hipStream_t stream() const = 0;
+  virtual const ic_problem& problem() const = 0;
   virtual void set_observation(const int32_t* counts, const void* response) = 0;
   virtual void forward(const void* s, void* delta, void* lambda, double* loss) = 0;
   virtual void loss_and_grad(const void* s, void* grad, ic_loss_terms* terms) = 0;
@@ -23,6 +25,10 @@ struct EngineBase {
   virtual void lbfgs_step(void* s, void* grad, double* loss, int64_t iteration,
                           ic_lbfgs_info* info) = 0;
   virtual void lbfgs_reset() = 0;
+  // Fine white noise from the coarse field s_low of engine low (same precision,
+  // half the particle grid side, same box): see ic_upsample_noise.
+  virtual void upsample_from(EngineBase& low, const void* s_low, void* s_high,
+                             uint64_t event) = 0;
   // single stages
   virtual void op_rfft(int grid, const void* x, void* xk) = 0;
   virtual void op_irfft(int grid, const void* xk, void* x) = 0;

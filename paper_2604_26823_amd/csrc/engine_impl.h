@@ -173,6 +173,9 @@ class Engine final : public EngineBase {
     timer_.set_stream(s);
   }
 
+  hipStream_t stream() const override { return st_; }
+  const ic_problem& problem() const override { return prob_; }
+
   void set_observation(const int32_t* counts, const void* response) override {
     if (!counts || !response) throw ApiError(IC_ERR_INVALID_ARG, "null observation buffer");
     counts_ = counts;
@@ -232,6 +235,46 @@ class Engine final : public EngineBase {
   void lbfgs_reset() override {
     free_slots_.insert(free_slots_.end(), hist_.begin(), hist_.end());
     hist_.clear();
+  }
+
+  // Fresh N(0,1) noise on this grid (Philox stream 4, counter (j, 0, 4, event),
+  // j the lattice index) whose modes inside the coarse band are replaced by
+  // the coarse field's, scaled.  The coarse forward transform runs on the
+  // low engine, on this engine's stream, into spare space of this engine's
+  // spectrum pool.
+  void upsample_from(EngineBase& low, const void* s_low, void* s_high,
+                     uint64_t event) override {
+    const ic_problem& lp = low.problem();
+    const int nl = lp.n_part;
+    if (nl * 2 != np_ || lp.box != prob_.box)
+      throw ApiError(IC_ERR_INVALID_ARG,
+                     "the coarse context needs half the particle grid side and the same box");
+    if (!s_low || !s_high) throw ApiError(IC_ERR_INVALID_ARG, "null field");
+    cx<T>* zl = pool_ + Hp_;  // dense coarse half spectrum (nl^2 (nl/2+1) < Hp_ entries)
+    const hipStream_t ls = low.stream();
+    low.set_stream(st_);
+    try {
+      low.op_rfft(0, s_low, zl);
+    } catch (...) {
+      low.set_stream(ls);
+      throw;
+    }
+    low.set_stream(ls);
+    T* out = static_cast<T*>(s_high);
+    fk::k_philox<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(0, 0, 4, event, prob_.seed,
+                                                                  out, P_);
+    IC_LAUNCHED();
+    auto f = fa(0);
+    fft_r2c_z<T>(f, out, T(1), nullptr, T(0), pool_);
+    fft_y<T>(f, pool_, true);
+    fft_x<T>(f, pool_, pool_, true, T(1));
+    const long long modes = (long long)nl * nl * (nl / 2);
+    fk::k_embed_coarse<T><<<grid_for(modes, kThreads), kThreads, 0, st_>>>(
+        zl, nl, pool_, np_, kpp_, static_cast<T>(std::pow((double)np_ / nl, 1.5)));
+    IC_LAUNCHED();
+    fft_x<T>(f, pool_, pool_, false, T(1.0 / (double)P_));
+    fft_y<T>(f, pool_, false);
+    fft_c2r_z<T>(f, pool_, out, T(1), nullptr, T(0));
   }
 
   // Spectra cross the ABI in the contiguous n x n x (n/2+1) layout.

@@ -298,6 +298,31 @@ __global__ void k_philox(int kind, uint64_t sub, uint64_t stream, uint64_t event
     out[i] = static_cast<T>(philox_draw(kind, (uint64_t)i, sub, stream, event, seed));
 }
 
+// White-noise upsampling (section 3, the resolution schedule): the modes of
+// a coarse field with every wave index strictly inside (-nl/2, nl/2) replace
+// those of a fine spectrum, times scale = (nh/nl)^{3/2} (the unnormalised DFT
+// of unit white noise grows as the cell count).  lo: dense coarse half
+// spectrum [nl][nl][nl/2+1]; hi: stored fine half spectrum [nh][nh][kp].  One
+// thread per coarse (i, j, kz < nl/2); the coarse Nyquist rows are skipped.
+template <typename T>
+__global__ void k_embed_coarse(const cx<T>* __restrict__ lo, int nl, cx<T>* __restrict__ hi,
+                               int nh, int kp, T scale) {
+  const int h = nl / 2;
+  const long long total = (long long)nl * nl * h;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int kz = static_cast<int>(t % h);
+    const long long r = t / h;
+    const int j = static_cast<int>(r % nl);
+    const int i = static_cast<int>(r / nl);
+    if (i == h || j == h) continue;
+    const int fi = i < h ? i : i + (nh - nl);
+    const int fj = j < h ? j : j + (nh - nl);
+    const cx<T> v = lo[((long long)i * nl + j) * (h + 1) + kz];
+    hi[((long long)fi * nh + fj) * kp + kz] = cscale<T>(v, scale);
+  }
+}
+
 // One projection pass: out = (x - mean) / std with mean = sum[0]/n and
 // std = sqrt(sq[0]/n); |out| > s_th is replaced by the reset draw of that
 // element (counter sub word = sub).  The reset count goes to part[block].
