@@ -213,15 +213,19 @@ int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
                          int32_t trial, ic_rom_info* info);
 
 /* One projected L-BFGS iteration (section 2.3.1): direction from the
- * two-loop recursion over the stored pairs (FP64 dot products), backtracking
+ * two-loop recursion over the stored pairs (FP64 dot products) with initial
+ * inverse Hessian gamma I, gamma = S.Y / Y.Y of the newest pair, or 1/|g|
+ * with an empty history (the first step of a fresh history, -g/|g|, has unit
+ * length), backtracking
  * line search along the projection arc s' = P(s + eps p) from eps_max,
  * halving, accepting when g.(s' - s) < 0, L(s') < L and
  * L(s') <= L + c1 g.(s' - s);
  * if that fails for a quasi-Newton direction, the history is reset and
  * steepest descent is searched once more.  Then the (S, Y) pair update.
  * s, grad: device in/out (n_part^3); loss: host in/out; iteration keys the
- * reset draws.  Returns IC_ERR_LINESEARCH when no trial passes (s, grad and
- * loss are then unchanged). */
+ * reset draws.  Returns IC_ERR_LINESEARCH when no trial passes or the
+ * gradient is zero (s, grad and loss are then unchanged), IC_ERR_NONFINITE
+ * when the gradient is not finite. */
 int ic_lbfgs_step(ic_ctx* ctx, void* s, void* grad, double* loss, int64_t iteration,
                   ic_lbfgs_info* info);
 

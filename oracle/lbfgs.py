@@ -12,10 +12,13 @@ g.(s' - s) < 0 and L(s') < L(s) (the last rejects steps the projection
 undoes, whose predicted decrease is rounding noise) (Bertsekas' rule for projected line searches: the projection
 rescales long steps, so the unprojected eps g.p would demand far more
 decrease than any projected step can give); initial inverse Hessian gamma I
-with gamma = S.Y / Y.Y of the newest pair (1 with an empty history, natural
-since the prior's Hessian is the identity); a pair is stored only when
+with gamma = S.Y / Y.Y of the newest pair, and 1/|g| with an empty history,
+so that the first step from a fresh history, -g/|g|, has unit length (the
+direction is written with a hat in section 2.3.1; the gradient's scale says
+nothing about the step's, above all without the prior term, where |g| grows
+with the galaxy count); a pair is stored only when
 S.Y > 1e-10 |S| |Y|; the history holds m = 10 pairs; a non-descent direction
-resets the history and falls back to -g, and so does a quasi-Newton
+resets the history and falls back to -g/|g|, and so does a quasi-Newton
 direction whose line search fails (trials then continue numbering from
 max_trials).  All dot products are FP64.
 """
@@ -53,7 +56,7 @@ class ProjectedLBFGS:
             a = rho * np.dot(S, q)
             q = q - a * Y
             alpha.append(a)
-        gamma = 1.0
+        gamma = 1.0 / np.linalg.norm(g)
         if self.S:
             gamma = np.dot(self.S[-1], self.Y[-1]) / np.dot(self.Y[-1], self.Y[-1])
         r = gamma * q
@@ -95,14 +98,14 @@ class ProjectedLBFGS:
         restarted = False
         if not gp < 0:
             self.reset()
-            p = -g
+            p = -g / np.linalg.norm(g)
             gp = float(np.dot(g, p))
             restarted = True
         accepted, trial, eps, s_t, g_t, L_t, resets = self._search(s, g, L, p, fun,
                                                                     iteration, 0)
         if not accepted and self.S:
             self.reset()
-            p = -g
+            p = -g / np.linalg.norm(g)
             gp = float(np.dot(g, p))
             restarted = True
             accepted, trial, eps, s_t, g_t, L_t, resets = self._search(

@@ -149,7 +149,11 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
   const double L = *loss;
   const int m = prob_.lbfgs_m;
   ic_lbfgs_info inf{};
-  // Two-loop recursion: dir = -H g with H0 = gamma I.
+  // Two-loop recursion: dir = -H g with H0 = gamma I; gamma = S.Y / Y.Y of
+  // the newest pair, or 1 / |g| with an empty history (a unit-length first step).
+  const double gnorm = std::sqrt(dot(g, g, P_));
+  if (!std::isfinite(gnorm)) throw ApiError(IC_ERR_NONFINITE, "gradient is not finite");
+  if (!(gnorm > 0)) throw ApiError(IC_ERR_LINESEARCH, "zero gradient: no descent direction");
   copy(g, dir_, P_);
   const int h = static_cast<int>(hist_.size());
   std::vector<double> alpha(h);
@@ -158,7 +162,7 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
     alpha[i] = hist_rho_[sl] * dot(hist_S_ + sl * P_, dir_, P_);
     axpy(dir_, hist_Y_ + sl * P_, -alpha[i], dir_, P_);
   }
-  const double gamma = h ? hist_sy_[hist_.back()] / hist_yy_[hist_.back()] : 1.0;
+  const double gamma = h ? hist_sy_[hist_.back()] / hist_yy_[hist_.back()] : 1.0 / gnorm;
   if (gamma != 1.0) axpy(dir_, dir_, gamma - 1.0, dir_, P_);
   for (int i = 0; i < h; ++i) {
     const int sl = hist_[i];
@@ -169,7 +173,7 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
   double gp = dot(g, dir_, P_);
   if (!(gp < 0)) {
     lbfgs_reset();
-    axpy(g, g, -2.0, dir_, P_);
+    axpy(g, g, -1.0 - 1.0 / gnorm, dir_, P_);
     gp = dot(g, dir_, P_);
     inf.restarted = 1;
   }
@@ -186,7 +190,7 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
     if (attempt == 1) {
       if (hist_.empty()) break;
       lbfgs_reset();
-      axpy(g, g, -2.0, dir_, P_);
+      axpy(g, g, -1.0 - 1.0 / gnorm, dir_, P_);
       gp = dot(g, dir_, P_);
       inf.restarted = 1;
     }

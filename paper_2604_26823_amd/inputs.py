@@ -18,7 +18,15 @@ available here; synthetic survey-shaped volumes stand in for it:
 * c3 - 256^3, 1000 Mpc/h, 10 steps, same geometry, about 8e6 galaxies;
 * c4 - 256^3 particles on a 512^3 force mesh, 1000 Mpc/h, 20 steps;
 * c5 - 512^3 particles on a 1024^3 mesh, 2000 Mpc/h, 20 steps, c3's
-  selection density.
+  selection density;
+* c6 - the paper's own scale (sections 2.1 and 2.2.1): Planck13 parameters,
+  256^3 particles and mesh in a 500 Mpc/h box whose centre lies 400 Mpc/h
+  from the observer along the box diagonal, 18 steps of 0.05 in a, a disk
+  footprint of 20 degrees half-opening between comoving distances 200 and
+  625 Mpc/h with the same radial selection shape, 1.06e6 galaxies, and the
+  Poisson likelihood of the power-law x sigmoid bias without the prior
+  term.  coarsen() gives its 4 Mpc/h data for the first level of the
+  resolution schedule.
 
 Seeds for configuration c: truth white noise 1000c+1, counts 1000c+2, start
 1000c+3, counter-generator key 1000c+4.  White noise is drawn in FP64,
@@ -30,12 +38,15 @@ import math
 import numpy as np
 
 __all__ = ["CONFIGS", "config", "white_noise", "response_field", "nbar_for",
-           "poisson_counts", "seeds"]
+           "poisson_counts", "seeds", "coarsen"]
 
 _COMMON = dict(a_init=0.1, a_final=1.0, omega_m=0.3, h=0.7, n_s=0.96, sigma8=0.8,
                bias=1.5, r_min=1e-3, prior_weight=1.0, observer=(0.0, 0.0, 0.0),
                lbfgs_m=10, eps_max=1.0, armijo_c1=1e-4, max_trials=30, s_th=10.0,
                rom_nbins=100, rom_kmin=0.1)
+
+# c6 observer: the box centre (250, 250, 250) lies 400 Mpc/h away along (1,1,1)/sqrt(3)
+_OBS6 = 250.0 - 400.0 / math.sqrt(3.0)
 
 CONFIGS = {
     1: dict(_COMMON, n_part=32, n_mesh=32, box=256.0, n_steps=5, rsd="z",
@@ -48,6 +59,10 @@ CONFIGS = {
             geometry="cone", galaxies=8.0e6, rom_every=20, iterations=20),
     5: dict(_COMMON, n_part=512, n_mesh=1024, box=2000.0, n_steps=20, rsd="radial",
             geometry="cone", galaxies=None, nbar_from=3, rom_every=20, iterations=50),
+    6: dict(_COMMON, n_part=256, n_mesh=256, box=500.0, n_steps=18, omega_m=0.315, h=0.673,
+            sigma8=0.829, rsd="radial", geometry="disk", galaxies=1.06e6, loss="poisson",
+            prior_weight=0.0, observer=(_OBS6, _OBS6, _OBS6), rom_every=20, iterations=3600,
+            low_rom_every=5, low_iterations=250),
 }
 
 
@@ -83,11 +98,19 @@ def _cone_inside(y):
     return (c0 > 0) & (np.abs(c1) <= t * c0) & (np.abs(c2) <= t * c0)
 
 
+def _disk_inside(y, r):
+    """Circular footprint of 20 degrees half-opening around (1,1,1)/sqrt(3),
+    comoving distance between 200 and 625 Mpc/h."""
+    c0 = np.tensordot(np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0), y, axes=1)
+    return (c0 >= math.cos(math.radians(20.0)) * r) & (r >= 200.0) & (r <= 625.0)
+
+
 def response_field(cfg):
     """Survey response R on the data grid (N_p^3), FP32-representable.
 
-    Nodes sit at c * (L / N_p).  'halfbox': R = 1 where x < L/2.  'cone':
-    R = exp(-(r/300)^1.5) inside the footprint seen from the observer."""
+    Nodes sit at c * (L / N_p).  'halfbox': R = 1 where x < L/2.  'cone' and
+    'disk': R = exp(-(r/300)^1.5) inside the footprint seen from the observer
+    (nodes of the box only: no periodic images)."""
     n, L = cfg["n_part"], cfg["box"]
     x = np.arange(n, dtype=np.float64) * (L / n)
     X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
@@ -97,8 +120,20 @@ def response_field(cfg):
         obs = np.asarray(cfg["observer"], dtype=np.float64)
         y = np.stack([X - obs[0], Y - obs[1], Z - obs[2]])
         r = np.sqrt(np.sum(y * y, axis=0))
-        R = np.where(_cone_inside(y), np.exp(-(r / 300.0) ** 1.5), 0.0)
+        inside = _cone_inside(y) if cfg["geometry"] == "cone" else _disk_inside(y, r)
+        R = np.where(inside, np.exp(-(r / 300.0) ** 1.5), 0.0)
     return R.astype(np.float32).astype(np.float64)
+
+
+def coarsen(counts, R):
+    """Data of a grid of half the side: counts summed and the response
+    averaged over each 2 x 2 x 2 group of cells (cells 2c and 2c+1 along each
+    axis), FP32-representable.  Integer counts stay integers; the coarse node
+    2c sits half a fine cell below the centre of its group."""
+    n = counts.shape[0] // 2
+    c = np.asarray(counts, dtype=np.int64).reshape(n, 2, n, 2, n, 2).sum(axis=(1, 3, 5))
+    r = np.asarray(R, dtype=np.float64).reshape(n, 2, n, 2, n, 2).mean(axis=(1, 3, 5))
+    return c.astype(np.int32), r.astype(np.float32).astype(np.float64)
 
 
 def nbar_for(cfg, R=None):

@@ -28,6 +28,20 @@
       cells, on the cells under the mask; the losses of s = 0 and of the
       truth for reference.
 
+  python -m paper_2604_26823_amd.studies schedule [--iterations 3600]
+          [--low-iterations 250] [--runs annealed,cold] [--out F]
+      The resolution schedule of section 3 at the paper's own scale (c6:
+      Planck13, 256^3 in 500 Mpc/h, 18 steps, disk footprint, 1.06e6
+      galaxies, Poisson likelihood of the power-law x sigmoid bias, no prior
+      term).  'annealed': projected L-BFGS on the 4 Mpc/h data (counts
+      summed over 2^3 cells) with rank-order matching every 5 iterations,
+      the result upsampled to 256^3 (large-scale modes kept, fresh small
+      scales), then full resolution with matching every 20.  'cold': full
+      resolution from a random start.  Per run: the loss every 50
+      iterations, evaluations, time, moments of the final noise, r_c(k) with
+      the truth and the masked correlation of both fields smoothed over 4
+      cells; the losses of s = 0 and of the truth for reference.
+
 Every output line is one JSON record (also appended to --out)."""
 import argparse
 import json
@@ -244,6 +258,32 @@ def _cross_correlation(a, b, box, nbins=10):
     return out
 
 
+def _optimise(ctx, s, g, L, iterations, rom_every, event0, curve_every, progress=None):
+    """Projected (or plain) L-BFGS from (s, g, L) in place; a rank-order
+    matching event (real, Fourier, projection, history reset) every
+    rom_every iterations when rom_every > 0.  Returns the loss curve, the
+    evaluation count, a status and the final loss."""
+    curve, evals, status = [[0, L]], 0, "ok"
+    for it in range(iterations):
+        try:
+            L, info = ctx.lbfgs_step(s, g, L, it)
+        except _lib.IcError as e:
+            status = "stopped at iteration %d: %s" % (it, e)
+            break
+        evals += info["evaluations"]
+        if rom_every and (it + 1) % rom_every == 0:
+            ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL | _lib.IC_ROM_FOURIER,
+                                  event=event0 + it + 1)
+            ctx.lbfgs_reset()
+            L, g, _ = ctx.loss_and_grad(s, g)
+            evals += 1
+        if (it + 1) % curve_every == 0:
+            curve.append([it + 1, L])
+            if progress:
+                progress(it + 1, L)
+    return curve, evals, status, L
+
+
 def ablation(a):
     import torch
 
@@ -275,23 +315,9 @@ def ablation(a):
         s = torch.tensor(s_start, dtype=ctx.dtype, device=ctx.device)
         ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
         L, g, _ = ctx.loss_and_grad(s)
-        curve, evals, status = [[0, L]], 1, "ok"
         t0 = time.perf_counter()
-        for it in range(a.iterations):
-            try:
-                L, info = ctx.lbfgs_step(s, g, L, it)
-            except _lib.IcError as e:
-                status = "stopped at iteration %d: %s" % (it, e)
-                break
-            evals += info["evaluations"]
-            if rom and (it + 1) % 20 == 0:
-                ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL
-                                      | _lib.IC_ROM_FOURIER, event=it + 1)
-                ctx.lbfgs_reset()
-                L, g, _ = ctx.loss_and_grad(s, g)
-                evals += 1
-            if (it + 1) % 10 == 0:
-                curve.append([it + 1, L])
+        curve, evals, status, L = _optimise(ctx, s, g, L, a.iterations, 20 if rom else 0, 0, 10)
+        evals += 1
         torch.cuda.synchronize()
         final = s.double().cpu().numpy()
         m = R >= base["r_min"]
@@ -303,6 +329,87 @@ def ablation(a):
         ctx.close()
         del ctx, s, g
         torch.cuda.empty_cache()
+
+
+def schedule(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    cfg = inputs.config(6)
+    R = inputs.response_field(cfg)
+    sd = inputs.seeds(6)
+    n = cfg["n_part"]
+    s_true = inputs.white_noise(n, sd["truth"])
+    work = "c6: 256^3, 500 Mpc/h, 18 steps, Planck13, disk footprint, Poisson, 1.06e6 galaxies"
+    # N-bar such that the truth's rate sums to the catalogue size over the
+    # mask (the rate is linear in N-bar), then the counts at that N-bar
+    cfg["nbar"] = 1.0
+    ctx = Context(cfg, "f32", "cuda:0")
+    _observe(ctx, R, np.zeros(R.shape, dtype=np.int32))
+    lam = ctx.forward(torch.tensor(s_true, dtype=ctx.dtype, device=ctx.device), delta=False,
+                      lam=True)["lambda"].double().cpu().numpy()
+    ctx.close()
+    del ctx
+    cfg["nbar"] = cfg["galaxies"] / float(lam[R >= cfg["r_min"]].sum())
+    counts = inputs.poisson_counts(lam * cfg["nbar"], R, cfg["r_min"], sd["counts"])
+    hi = Context(cfg, "f32", "cuda:0")
+    _observe(hi, R, counts)
+    m = R >= cfg["r_min"]
+    zero = torch.zeros(hi.grid, dtype=hi.dtype, device=hi.device)
+    _emit(dict(study="schedule", workload=work, run="homogeneous s = 0",
+               loss=hi.loss_and_grad(zero)[0], galaxies=int(counts.sum()), nbar=cfg["nbar"]),
+          a.out)
+    st = torch.tensor(s_true, dtype=hi.dtype, device=hi.device)
+    _emit(dict(study="schedule", workload=work, run="truth s_true",
+               loss=hi.loss_and_grad(st)[0]), a.out)
+    del zero, st
+
+    def progress(tag):
+        return lambda it, L: print("%s iteration %d loss %.6e" % (tag, it, L), flush=True)
+
+    def report(name, s, curve, evals, status, L, seconds, extra):
+        final = s.double().cpu().numpy()
+        corr = float(np.corrcoef(_smooth(final, 4.0)[m], _smooth(s_true, 4.0)[m])[0, 1])
+        _emit(dict(study="schedule", workload=work, run=name, status=status, final_loss=L,
+                   evaluations=evals, seconds=seconds, loss_curve=curve,
+                   white_noise=_white_noise_stats(final), corr_masked=corr,
+                   r_c=_cross_correlation(final, s_true, cfg["box"]), **extra), a.out)
+
+    for run in a.runs.split(","):
+        t0 = time.perf_counter()
+        extra = {}
+        if run == "annealed":
+            low_cfg = dict(cfg, n_part=n // 2, n_mesh=n // 2, nbar=8.0 * cfg["nbar"])
+            Nl, Rl = inputs.coarsen(counts, R)
+            lo = Context(low_cfg, "f32", "cuda:0")
+            _observe(lo, Rl, Nl)
+            sl = torch.tensor(inputs.white_noise(n // 2, sd["start"]), dtype=lo.dtype,
+                              device=lo.device)
+            lo.project_rankmatch(sl, _lib.IC_PROJECT, event=0, trial=0)
+            L, g, _ = lo.loss_and_grad(sl)
+            lcurve, levals, lstatus, L = _optimise(lo, sl, g, L, a.low_iterations,
+                                                   cfg["low_rom_every"], 0, 10,
+                                                   progress("low"))
+            torch.cuda.synchronize()
+            extra.update(low=dict(cells=n // 2, final_loss=L, evaluations=levals + 1,
+                                  status=lstatus, loss_curve=lcurve,
+                                  seconds=time.perf_counter() - t0))
+            s = hi.upsample_from(lo, sl, 1)
+            lo.close()
+            del lo, sl, g
+            torch.cuda.empty_cache()
+        else:
+            s = torch.tensor(inputs.white_noise(n, sd["start"]), dtype=hi.dtype, device=hi.device)
+        hi.lbfgs_reset()
+        hi.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+        L, g, _ = hi.loss_and_grad(s)
+        extra["start_loss"] = L
+        curve, evals, status, L = _optimise(hi, s, g, L, a.iterations, cfg["rom_every"], 100000,
+                                            50, progress(run))
+        torch.cuda.synchronize()
+        report(run, s, curve, evals + 1, status, L, time.perf_counter() - t0, extra)
+        del s, g
+    hi.close()
 
 
 def main():
@@ -319,10 +426,14 @@ def main():
     sc.add_argument("--tape-forces", type=int, default=0)
     sc.add_argument("--profile", action="store_true")
     sc.add_argument("--skip-f64", action="store_true")
-    for p in (pr, sc, ab):
+    sh = sub.add_parser("schedule")
+    sh.add_argument("--iterations", type=int, default=inputs.config(6)["iterations"])
+    sh.add_argument("--low-iterations", type=int, default=inputs.config(6)["low_iterations"])
+    sh.add_argument("--runs", default="annealed,cold")
+    for p in (pr, sc, ab, sh):
         p.add_argument("--out", default="")
     a = ap.parse_args()
-    {"precision": precision, "scale": scale, "ablation": ablation}[a.mode](a)
+    {"precision": precision, "scale": scale, "ablation": ablation, "schedule": schedule}[a.mode](a)
 
 
 if __name__ == "__main__":

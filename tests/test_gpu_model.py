@@ -39,6 +39,9 @@ CASES = {
     "poisson_c1": dict(c=1, loss="poisson"),
     "poisson_radial32": dict(c=2, n_part=32, n_mesh=32, box=128.0, n_steps=5, galaxies=2e4,
                              loss="poisson", prior_weight=0.0),
+    # the paper-scale geometry (observer inside the 500 Mpc/h box, disk footprint,
+    # Planck13, Poisson without prior) on a 32^3 lattice
+    "disk32": dict(c=6, n_part=32, n_mesh=32, n_steps=4, galaxies=2e4),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}

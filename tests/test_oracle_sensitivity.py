@@ -3,7 +3,7 @@
 This is the property that bounds how closely any finite-precision
 implementation can follow the FP64 oracle's loss trajectory: a 1e-7
 relative perturbation of the start field grows by orders of magnitude within
-a few iterations on c1 (32^3, 8 Mpc/h cells, half-box mask)."""
+a dozen iterations on c1 (32^3, 8 Mpc/h cells, half-box mask)."""
 import numpy as np
 
 from oracle import lbfgs, projection
@@ -24,7 +24,7 @@ def test_oracle_trajectory_sensitivity():
         L, g, _ = mdl.loss_and_grad(x.reshape(32, 32, 32), N, R)
         return L, g.reshape(-1)
 
-    def run(start, iters=5):
+    def run(start, iters=12):
         s, _ = projection.project(start, 10.0, cfg["seed"], 0, 0)
         L, g = fun(s)
         s = s.reshape(-1)
@@ -39,4 +39,4 @@ def test_oracle_trajectory_sensitivity():
     b = run(s0 * (1 + 1e-7 * np.random.default_rng(1).standard_normal(s0.shape)))
     rel = np.abs(a - b) / np.abs(a)
     assert rel[0] < 1e-7
-    assert rel[-1] > 30 * rel[0]
+    assert rel[-1] > 1000 * rel[0]

@@ -51,3 +51,45 @@ def test_library_header_defaults():
     assert define("IC_DEFAULT_ROM_KMIN") == g["rom_kmin"]
     assert define("IC_DEFAULT_A_INIT") == g["a_init"]
     assert define("IC_DEFAULT_EPS_MAX") == g["eps_max"]
+
+
+def test_paper_scale_workload():
+    """c6 carries the paper's own volume, cosmology, time grid, footprint,
+    catalogue size, observation model and schedule."""
+    import math
+
+    import numpy as np
+    g = golden()
+    c = inputs.config(6)
+    for k in ("sigma8", "h", "omega_m", "box", "n_part", "n_steps", "galaxies"):
+        assert c[k] == g[k], k
+    from oracle.model import Problem
+    p = Problem(n_part=8, n_mesh=8, box=1.0)
+    assert (p.bias_alpha, p.bias_delta_th, p.bias_k) == (g["bias_alpha"], g["bias_delta_th"],
+                                                        g["bias_k"])
+    assert c["n_mesh"] == c["n_part"]
+    assert abs((c["a_final"] - c["a_init"]) / c["n_steps"] - 0.05) < 1e-12
+    assert c["iterations"] == g["iterations"] and c["low_iterations"] == g["low_iterations"]
+    assert c["rom_every"] == g["rom_every"] and c["low_rom_every"] == g["rom_every_lowres"]
+    assert abs(c["box"] / (c["n_part"] // 2) - g["low_cell"]) < 0.1
+    assert c["loss"] == "poisson" and c["prior_weight"] == 0.0
+    obs = np.asarray(c["observer"])
+    centre = np.full(3, c["box"] / 2)
+    assert abs(np.linalg.norm(centre - obs) - g["centre_distance"]) < 1e-9
+    # footprint: every node with a response lies within the disk and the
+    # distance range, and the disk is filled out to its edge
+    R = inputs.response_field(dict(c, n_part=64))
+    n = 64
+    x = np.arange(n) * (c["box"] / n)
+    y = np.stack(np.meshgrid(x, x, x, indexing="ij")) - obs[:, None, None, None]
+    r = np.sqrt((y * y).sum(axis=0))
+    ang = np.degrees(np.arccos(np.clip(y.sum(axis=0) / (math.sqrt(3) * np.maximum(r, 1e-9)),
+                                       -1, 1)))
+    m = R > 0
+    assert ang[m].max() <= g["half_opening"] + 1e-9 and ang[m].max() > g["half_opening"] - 1.5
+    assert r[m].min() >= 200.0 and r[m].max() <= 625.0
+    # the coarse data keep every galaxy and the mean response
+    counts = np.random.default_rng(0).poisson(2.0, (n, n, n)).astype(np.int32)
+    cc, rc = inputs.coarsen(counts, R)
+    assert cc.shape == (n // 2,) * 3 and cc.sum() == counts.sum()
+    assert abs(rc.mean() - R.mean()) <= 1e-6 * R.mean()
