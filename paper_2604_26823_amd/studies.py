@@ -232,7 +232,8 @@ def _smooth(x, cells):
     jz = np.arange(n // 2 + 1)
     k2 = (2 * np.pi / n) ** 2 * (j[:, None, None] ** 2 + j[None, :, None] ** 2
                                  + jz[None, None, :] ** 2)
-    return np.fft.irfftn(np.fft.rfftn(x) * np.exp(-0.5 * k2 * cells ** 2), s=x.shape)
+    return np.fft.irfftn(np.fft.rfftn(x) * np.exp(-0.5 * k2 * cells ** 2), s=x.shape,
+                         axes=(0, 1, 2))
 
 
 def _cross_correlation(a, b, box, nbins=10):
