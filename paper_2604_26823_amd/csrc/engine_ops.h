@@ -82,7 +82,7 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
   fft_x<T>(f, Z, Z, true, T(1));
   const double n3h = std::pow((double)np_, 1.5);
   const int nbins = prob_.rom_nbins;
-  if (nbins < 1 || nbins > 254) throw ApiError(IC_ERR_INVALID_ARG, "rom_nbins must be in [1, 254]");
+  if (nbins < 1 || nbins > 127) throw ApiError(IC_ERR_INVALID_ARG, "rom_nbins must be in [1, 127]");
   const double kf = 2.0 * 3.14159265358979323846 / prob_.box;
   const double kmax = std::sqrt(3.0) * 3.14159265358979323846 * np_ / prob_.box;
   const double dk = (kmax - prob_.rom_kmin) / nbins;
@@ -98,11 +98,18 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
   radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hq_, 8, st_);
   ek::k_fill_u32<<<1, 256, 0, st_>>>(binc_, 0u, 256);
   IC_LAUNCHED();
-  rk::k_bin_count<<<G, kThreads, 0, st_>>>(keys_, binc_, Hq_);
+  rk::k_bin_ends<<<G, kThreads, 0, st_>>>(keys_, binc_, Hq_);
   IC_LAUNCHED();
   std::vector<uint32_t>& counts = bin_count_;
   IC_HIP(hipMemcpyAsync(counts.data(), binc_, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
   IC_HIP(hipStreamSynchronize(st_));
+  // run ends -> counts (bins are sorted ascending; absent bins read 0)
+  for (uint32_t b = 0, prev = 0; b < 255; ++b) {
+    if (counts[b] == 0) continue;
+    const uint32_t e = counts[b];
+    counts[b] = e - prev;
+    prev = e;
+  }
   std::vector<uint32_t>& start = bin_start_;
   std::fill(start.begin(), start.end(), 0u);
   long long n = 0;

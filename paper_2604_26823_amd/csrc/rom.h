@@ -97,13 +97,17 @@ __global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, int kp, T scale,
   }
 }
 
-// Counts of each bin over the sorted second keys (bins < 255).
-static __global__ void k_bin_count(const uint64_t* __restrict__ bins, uint32_t* __restrict__ counts,
-                            long long n) {
+// End (last position + 1) of each bin's run in the bin-sorted keys, for
+// bins < 255; entries of absent bins are left as they are (zero-filled by
+// the caller).  The last element of a run is its only writer, so no atomics:
+// a histogram by atomics serialises on the sorted input, where every lane of
+// a wavefront hits the same counter.
+static __global__ void k_bin_ends(const uint64_t* __restrict__ bins, uint32_t* __restrict__ ends,
+                                  long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const uint64_t b = bins[i];
-    if (b < 255) atomicAdd(&counts[b], 1u);
+    if (b < 255 && (i + 1 == n || bins[i + 1] != b)) ends[b] = static_cast<uint32_t>(i + 1);
   }
 }
 
