@@ -11,6 +11,9 @@ synthetic configurations:
    force F = -grad lap^-1 delta_m on the mesh and CIC readout           (item 2)
 4. RSD at a_final: shift c (p . d) d with d the line of sight from the
    observer (radial) or the z axis (plane parallel); c = 1/(a^2 E)       (item 3)
+   -- or, with snapshot scale factors given, at each particle's lightcone
+   crossing a_i (item 3, appendix A; ``oracle.lightcone``), the snapshots
+   being the kick-synchronised states at those steps.
 5. CIC of the shifted particles on the data grid -> delta_s; bias and
    response (items 4-5): linear, lambda = Nbar R (1 + b delta_s), or the
    paper's power law times a sigmoid (item 4, eq. of the galaxy bias),
@@ -31,6 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import cic, cosmology, fourier
+from .lightcone import Lightcone
 
 __all__ = ["Problem", "Model"]
 
@@ -58,6 +62,8 @@ class Problem:
     bias_alpha: float = 0.7        # power-law index alpha (section 2.2.1, item 4)
     bias_delta_th: float = 1.2     # sigmoid threshold delta_th
     bias_k: float = 3.0            # sigmoid steepness K
+    lightcone: tuple = ()          # snapshot scale factors, ascending, last a_final; () = off
+    lc_iterations: int = 3         # fixed-point iterations of the crossing scale factor
 
 
 class Model:
@@ -76,6 +82,22 @@ class Model:
         qx, qy, qz = np.meshgrid(j, j, j, indexing="ij")
         self.q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()])
         self._mult = {}
+        self.snap_steps = []
+        self.lc = None
+        if prob.lightcone:
+            S = prob.n_steps
+            a_n = prob.a_init + np.arange(S + 1) * (prob.a_final - prob.a_init) / S
+            la = list(prob.lightcone)
+            if abs(la[-1] - prob.a_final) > 1e-9 or any(b <= a for a, b in zip(la, la[1:])):
+                raise ValueError("snapshots must ascend and end at a_final")
+            for a in la[:-1]:
+                m = int(np.argmin(np.abs(a_n - a)))
+                if abs(a_n[m] - a) > 1e-9 or m < 1 or m >= S:
+                    raise ValueError("snapshot a = %g is not an interior step" % a)
+                self.snap_steps.append(m)
+            self.lc = Lightcone(self.q, prob.box, prob.observer, prob.omega_m,
+                                [a_n[m] for m in self.snap_steps] + [prob.a_final],
+                                prob.lc_iterations)
 
     # ------------------------------------------------------------ multipliers
     def mult(self, kind, axis=None, mesh=False):
@@ -134,11 +156,13 @@ class Model:
         return [K1[0]] + [K2[n - 1] + K1[n] for n in range(1, S)] + [K2[S - 1]]
 
     # -------------------------------------------------------------------- KDK
-    def evolve(self, d0, p0):
+    def evolve(self, d0, p0, snaps=None):
         """Kick-drift-kick with merged half kicks; returns the tape of
-        displacements d_0..d_S, force meshes g_0..g_S and final momentum."""
+        displacements d_0..d_S, force meshes g_0..g_S and final momentum.
+        With a list snaps, the synchronised states (d_m, p_m) of the snapshot
+        steps m are appended to it (p_m = p_{m-1/2} + K2_{m-1} F(d_m))."""
         kc = self.kick_coefficients()
-        Dr = self.coef["Dr"]
+        Dr, K2 = self.coef["Dr"], self.coef["K2"]
         d, p = d0.copy(), p0.copy()
         F, g = self.force(d)
         p = p + kc[0] * F
@@ -146,10 +170,19 @@ class Model:
         for n in range(self.p.n_steps):
             d = d + Dr[n] * p
             F, g = self.force(d)
+            if snaps is not None and n + 1 in self.snap_steps:
+                snaps.append((d.copy(), p + K2[n] * F))
             p = p + kc[n + 1] * F
             tape_d.append(d)
             tape_g.append(g)
         return d, p, tape_d, tape_g
+
+    def redshift_space(self, dS, pS, snaps):
+        """Redshift-space displacements: at a_final, or on the lightcone."""
+        if self.lc is None:
+            return self.rsd(dS, pS), None
+        ds, lc_state = self.lc.forward(list(snaps) + [(dS, pS)], self.p.rsd)
+        return ds, lc_state
 
     # -------------------------------------------------------------------- RSD
     def line_of_sight(self, d):
@@ -203,8 +236,9 @@ class Model:
         """L(s) = 1/2 chi^2 + 1/2 w_prior |s|^2, with everything the adjoint needs."""
         s = np.asarray(s, dtype=np.float64)
         d0, p0, lpt = self.lpt(s)
-        dS, pS, tape_d, tape_g = self.evolve(d0, p0)
-        ds = self.rsd(dS, pS)
+        snaps = []
+        dS, pS, tape_d, tape_g = self.evolve(d0, p0, snaps)
+        ds, lc_state = self.redshift_space(dS, pS, snaps)
         delta_s = self.data_density(ds)
         lam = self.observe(delta_s, response)
         chi2 = self.chi2(lam, counts, response)
@@ -214,13 +248,14 @@ class Model:
             return L
         return L, dict(lpt=lpt, d0=d0, p0=p0, dS=dS, pS=pS, tape_d=tape_d,
                        tape_g=tape_g, ds=ds, delta_s=delta_s, lam=lam,
-                       chi2=chi2, prior=prior)
+                       chi2=chi2, prior=prior, snaps=snaps, lc=lc_state)
 
     def forward(self, s):
         """s -> delta_s (the redshift-space data-grid overdensity)."""
         d0, p0, _ = self.lpt(np.asarray(s, dtype=np.float64))
-        dS, pS, _, _ = self.evolve(d0, p0)
-        return self.data_density(self.rsd(dS, pS))
+        snaps = []
+        dS, pS, _, _ = self.evolve(d0, p0, snaps)
+        return self.data_density(self.redshift_space(dS, pS, snaps)[0])
 
     # ---------------------------------------------------------------- adjoint
     def loss_seed(self, lam, counts, response, delta_s=None):
@@ -277,11 +312,27 @@ class Model:
         Dr = c["Dr"]
         kc = self.kick_coefficients()
         xs_bar = cic.readout_gradient(self.q + st["ds"], delta_bar, self.dq)
-        d_bar, p_bar = self.rsd_vjp(st["dS"], st["pS"], xs_bar)
+        snap_bar = {}
+        if self.lc is None:
+            d_bar, p_bar = self.rsd_vjp(st["dS"], st["pS"], xs_bar)
+        else:
+            snaps = list(st["snaps"]) + [(st["dS"], st["pS"])]
+            db, pb = self.lc.vjp(snaps, self.p.rsd, st["lc"], xs_bar)
+            d_bar, p_bar = db[-1], pb[-1]
+            snap_bar = {m: (db[j], pb[j]) for j, m in enumerate(self.snap_steps)}
         S = self.p.n_steps
+        K2 = c["K2"]
         for n in range(S - 1, -1, -1):
-            d_bar = d_bar + self.force_vjp(st["tape_d"][n + 1], st["tape_g"][n + 1],
-                                           kc[n + 1] * p_bar)
+            m = n + 1
+            v = kc[m] * p_bar
+            if m in snap_bar:
+                # snapshot (d_m, p_{m-1/2} + K2_{m-1} F(d_m))
+                sd, sp = snap_bar[m]
+                d_bar = d_bar + sd
+                v = v + K2[m - 1] * sp
+            d_bar = d_bar + self.force_vjp(st["tape_d"][m], st["tape_g"][m], v)
+            if m in snap_bar:
+                p_bar = p_bar + snap_bar[m][1]
             p_bar = p_bar + Dr[n] * d_bar
         d_bar = d_bar + self.force_vjp(st["tape_d"][0], st["tape_g"][0], kc[0] * p_bar)
         return self.lpt_vjp(st["lpt"], d_bar, p_bar)
@@ -321,7 +372,9 @@ class Model:
 
     # -------------------------------------------------------------------- JVP
     def jvp(self, s, ds):
-        """Tangent of delta_s along the white-noise tangent ds."""
+        """Tangent of delta_s along the white-noise tangent ds (no lightcone)."""
+        if self.lc is not None:
+            raise NotImplementedError("the tangent model has no lightcone")
         c = self.coef
         s = np.asarray(s, dtype=np.float64)
         d0, p0, lpt = self.lpt(s)
