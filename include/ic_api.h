@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IC_ABI_VERSION 4
+#define IC_ABI_VERSION 5
 
 #define IC_OK 0
 #define IC_ERR_INVALID_ARG (-1)
@@ -86,6 +86,12 @@ extern "C" {
 #define IC_DEFAULT_BIAS_DELTA_TH 1.2
 #define IC_DEFAULT_BIAS_K 3.0
 
+/* Lightcone (section 2.2.1 item 3, appendix A): at most this many snapshots;
+ * the paper saves a = 0.8, 0.9, 1.0 and iterates the crossing scale factor
+ * three times. */
+#define IC_MAX_SNAPSHOTS 4
+#define IC_DEFAULT_LC_ITERATIONS 3
+
 /* The reconstruction problem (sections 2.2-2.3).  Lengths in Mpc/h. */
 typedef struct ic_problem {
   int32_t n_part;        /* particles per side = white-noise and data grid side */
@@ -123,6 +129,19 @@ typedef struct ic_problem {
   int32_t project_steps; /* 1: trial points P(s + eps p) (the method, section 2.3.1);
                             0: plain L-BFGS trial points s + eps p (the ablation's
                             baseline, appendix B) */
+  int32_t lc_n;          /* lightcone (section 2.2.1 item 3, appendix A): number of
+                            snapshots, 0 = off (RSD and data paint at a_final), else
+                            1..IC_MAX_SNAPSHOTS */
+  int32_t lc_iterations; /* fixed-point iterations of the crossing scale factor (3) */
+  double lc_a[4];        /* snapshot scale factors, ascending; lc_a[lc_n-1] = a_final and
+                            the others interior steps a_m, 1 <= m < n_steps.  Each
+                            particle's displacement and momentum are interpolated
+                            linearly in a between the kick-synchronised snapshots; its
+                            scale factor a_i = DistToScaleFactor(|x(a_i) - observer|),
+                            iterated lc_iterations times from a_final and clamped to
+                            [lc_a[0], a_final], sets where it is painted and its RSD
+                            factor 1/(a_i^2 E(a_i)).  Distances: box-wrapped positions,
+                            flat-cosmology comoving distance with c/H0 = 2997.92458 */
 } ic_problem;
 
 typedef struct ic_loss_terms {

@@ -46,7 +46,8 @@ class IcProblem(ctypes.Structure):
         ("rom_kmin", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("bias_alpha", ctypes.c_double), ("bias_delta_th", ctypes.c_double),
         ("bias_k", ctypes.c_double), ("loss_kind", ctypes.c_int32),
-        ("project_steps", ctypes.c_int32),
+        ("project_steps", ctypes.c_int32), ("lc_n", ctypes.c_int32),
+        ("lc_iterations", ctypes.c_int32), ("lc_a", ctypes.c_double * 4),
     ]
 
 

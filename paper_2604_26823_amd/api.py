@@ -33,6 +33,14 @@ def make_problem(cfg):
     if "observer" in cfg:
         for a in range(3):
             p.observer[a] = float(cfg["observer"][a])
+    lc = cfg.get("lightcone") or ()
+    if len(lc) > 4:
+        raise ValueError("at most 4 lightcone snapshots")
+    p.lc_n = len(lc)
+    for j, a in enumerate(lc):
+        p.lc_a[j] = float(a)
+    if cfg.get("lc_iterations") is not None:
+        p.lc_iterations = int(cfg["lc_iterations"])
     return p
 
 

@@ -1,6 +1,7 @@
 // extern "C" entry points (include/ic_api.h, include/ic_ops.h): argument
 // validation, precision dispatch and the translation of exceptions into
 // status codes.  No exception or abort crosses the ABI.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -76,6 +77,25 @@ void validate_problem(const ic_problem& p) {
     bad(IC_ERR_INVALID_ARG, "unknown loss_kind");
   if (p.loss_kind == IC_LOSS_POISSON && !(p.bias_alpha > 0 && p.bias_k > 0))
     bad(IC_ERR_INVALID_ARG, "bias_alpha and bias_k must be positive");
+  if (p.lc_n < 0 || p.lc_n > IC_MAX_SNAPSHOTS) bad(IC_ERR_INVALID_ARG, "lc_n must be in [0, 4]");
+  if (p.lc_n > 0) {
+    if (p.lc_iterations < 1 || p.lc_iterations > 16)
+      bad(IC_ERR_INVALID_ARG, "lc_iterations must be in [1, 16]");
+    if (std::fabs(p.lc_a[p.lc_n - 1] - p.a_final) > 1e-9)
+      bad(IC_ERR_INVALID_ARG, "the last snapshot must be at a_final");
+    for (int j = 0; j + 1 < p.lc_n; ++j) {
+      if (!(p.lc_a[j] < p.lc_a[j + 1])) bad(IC_ERR_INVALID_ARG, "snapshots must ascend");
+      if (snapshot_step(p, p.lc_a[j]) < 0)
+        bad(IC_ERR_INVALID_ARG, "snapshots must sit on interior steps a_m, 1 <= m < n_steps");
+    }
+  }
+}
+
+int snapshot_step(const ic_problem& p, double a) {
+  const double da = (p.a_final - p.a_init) / p.n_steps;
+  const long m = std::lround((a - p.a_init) / da);
+  if (m < 1 || m >= p.n_steps || std::fabs(p.a_init + m * da - a) > 1e-9) return -1;
+  return static_cast<int>(m);
 }
 
 size_t workspace_bytes(const ic_problem& p, int precision) {
@@ -128,6 +148,8 @@ void ic_problem_defaults(ic_problem* p) {
   p->bias_delta_th = IC_DEFAULT_BIAS_DELTA_TH;
   p->bias_k = IC_DEFAULT_BIAS_K;
   p->project_steps = 1;
+  p->lc_n = 0;
+  p->lc_iterations = IC_DEFAULT_LC_ITERATIONS;
   p->rom_kmin = IC_DEFAULT_ROM_KMIN;
   p->seed = 0;
 }

@@ -181,4 +181,40 @@ std::vector<double> whitening_table(const CosmoParams& p, double amplitude, doub
   return w;
 }
 
+double comoving_distance(double omega_m, double a) {
+  constexpr double kCH0 = 2997.92458;
+  constexpr int kN = 4096;
+  if (a >= 1.0) return 0.0;
+  const double h = (1.0 - a) / kN;
+  auto f = [&](double x) { return 1.0 / (x * x * hubble_E(x, omega_m)); };
+  double s = f(a) + f(1.0);
+  for (int i = 1; i < kN; ++i) s += (i % 2 ? 4.0 : 2.0) * f(a + i * h);
+  return kCH0 * s * h / 3.0;
+}
+
+LightconeTable lightcone_table(double omega_m, double a_lo, double a_hi, int n) {
+  constexpr double kCH0 = 2997.92458;
+  constexpr int kSub = 64;
+  LightconeTable t;
+  t.chi_min = comoving_distance(omega_m, a_hi);
+  t.chi_max = comoving_distance(omega_m, a_lo);
+  t.h = (t.chi_max - t.chi_min) / (n - 1);
+  auto rate = [&](double a) { return -a * a * hubble_E(a, omega_m) / kCH0; };
+  t.a.resize(n);
+  t.slope.resize(n);
+  double a = a_hi;
+  const double dc = t.h / kSub;
+  for (int k = 0; k < n; ++k) {
+    t.a[k] = a;
+    t.slope[k] = rate(a);
+    if (k + 1 == n) break;
+    for (int i = 0; i < kSub; ++i) {
+      const double k1 = rate(a), k2 = rate(a + 0.5 * dc * k1), k3 = rate(a + 0.5 * dc * k2),
+                   k4 = rate(a + dc * k3);
+      a += dc * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+    }
+  }
+  return t;
+}
+
 }  // namespace ic

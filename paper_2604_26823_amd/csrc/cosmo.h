@@ -36,4 +36,20 @@ void growth_at(const CosmoParams& p, const std::vector<double>& a, std::vector<d
 
 double bbks_power_unnormalised(const CosmoParams& p, double k);
 
+// Comoving distance chi(a) = (c/H0) int_a^1 da' / (a'^2 E(a')) in Mpc/h
+// (c/H0 = 2997.92458 Mpc/h), composite Simpson over 4096 intervals.
+double comoving_distance(double omega_m, double a);
+
+// Inverse comoving distance for the lightcone (section 2.2.1 item 3,
+// appendix A): a(chi) on n nodes chi_k = chi_min + k h spanning
+// [chi(a_hi), chi(a_lo)], with slopes da/dchi = -a^2 E(a) / (c/H0), for
+// cubic Hermite interpolation.  The values come from the ODE
+// da/dchi = -a^2 E / (c/H0) integrated by classical Runge-Kutta (64 substeps
+// per node interval) from a(chi_min) = a_hi.
+struct LightconeTable {
+  double chi_min = 0, chi_max = 0, h = 0;
+  std::vector<double> a, slope;
+};
+LightconeTable lightcone_table(double omega_m, double a_lo, double a_hi, int n);
+
 }  // namespace ic

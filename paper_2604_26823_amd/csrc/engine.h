@@ -57,6 +57,9 @@ EngineBase* make_engine(const ic_problem& p, int precision, void* ws, size_t ws_
 // Shape / parameter validation shared by ic_workspace_size and ic_create.
 void validate_problem(const ic_problem& p);
 
+// Step m (1 <= m < n_steps) whose scale factor a_m equals a, else -1.
+int snapshot_step(const ic_problem& p, double a);
+
 template <typename T>
 size_t workspace_bytes_t(const ic_problem& p);
 template <typename T>

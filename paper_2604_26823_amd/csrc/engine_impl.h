@@ -16,6 +16,7 @@
 #include "fft.h"
 #include "fields.h"
 #include "blocks.h"
+#include "lightcone.h"
 #include "particles.h"
 #include "sort.h"
 #include "timer.h"
@@ -146,6 +147,15 @@ class Engine final : public EngineBase {
     dbg_idx_[1] = c.take<uint32_t>(Hq_);
     dbg_key_[1] = c.take<T>(Hq_);
     dbg_bin_ = c.take<uint32_t>(Hq_);
+    // Lightcone: the snapshots before the last (lattice order, 6 fields) and
+    // their cotangents, and the inverse comoving-distance table.
+    lc_on_ = p.lc_n >= 2;
+    if (lc_on_) {
+      for (int j = 0; j + 1 < p.lc_n; ++j) lc_steps_.push_back(snapshot_step(p, p.lc_a[j]));
+      snap_ = c.take<T>(lc_steps_.size() * 6 * P_);
+      snapbar_ = c.take<T>(lc_steps_.size() * 6 * P_);
+      lct_ = c.take<double>(2 * kLcNodes);
+    }
     need_ = c.used();
     if (!ws) return;
     if (ws_bytes < need_) throw ApiError(IC_ERR_WORKSPACE, "workspace too small");
@@ -162,6 +172,23 @@ class Engine final : public EngineBase {
     IC_HIP(hipMemcpyAsync(wtab_, wt.data(), wt.size() * sizeof(T), hipMemcpyHostToDevice, st_));
     IC_HIP(hipMemcpyAsync(twp_, tp.data(), tp.size() * sizeof(cx<T>), hipMemcpyHostToDevice, st_));
     IC_HIP(hipMemcpyAsync(twm_, tm.data(), tm.size() * sizeof(cx<T>), hipMemcpyHostToDevice, st_));
+    if (lc_on_) {
+      const LightconeTable t = lightcone_table(p.omega_m, p.lc_a[0], p.a_final, kLcNodes);
+      IC_HIP(hipMemcpyAsync(lct_, t.a.data(), kLcNodes * sizeof(double), hipMemcpyHostToDevice,
+                            st_));
+      IC_HIP(hipMemcpyAsync(lct_ + kLcNodes, t.slope.data(), kLcNodes * sizeof(double),
+                            hipMemcpyHostToDevice, st_));
+      lk::LcGeo& g = lcgeo_;
+      for (int j = 0; j < lk::kMaxSnap; ++j) g.a_snap[j] = j < p.lc_n ? p.lc_a[j] : 0.0;
+      g.a_snap[p.lc_n - 1] = p.a_final;
+      for (int j = 0; j + 1 < p.lc_n; ++j) g.a_snap[j] = co_.a[lc_steps_[j]];
+      g.J = p.lc_n;
+      g.iterations = p.lc_iterations;
+      g.om = p.omega_m;
+      g.c_final = co_.rsd_factor;
+      g.tab = lk::LcTable{lct_, lct_ + kLcNodes, t.chi_min, t.chi_max, t.h, 1.0 / t.h,
+                          kLcNodes, p.lc_a[0], p.a_final};
+    }
     IC_HIP(hipStreamSynchronize(st_));
   }
 
@@ -728,6 +755,15 @@ class Engine final : public EngineBase {
       scatter(mesh_order(n + 1), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(n + 1), pslot(n + 1)),
               6, ids(n), ids(n + 1), dest(n));
       force_mesh(n + 1, gslot(n + 1));
+      const int j = snapshot_index(n + 1);
+      if (j >= 0) {
+        // state n + 1 synchronised: p_{n+1/2} + K2_n F(d_{n+1})
+        auto sc = timer_.scope("lc_snapshot", P_ * (12.0 * sizeT() + 4.0) + 3.0 * M_ * sizeT());
+        lk::k_snapshot<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+            dslot(n + 1), pslot(n + 1), gslot(n + 1), M_, static_cast<T>(co_.K2[n]), ids(n + 1),
+            snap_ + (size_t)j * 6 * P_, P_, lp_, gmesh());
+        IC_LAUNCHED();
+      }
     }
     seg_ = K_ ? S_ - S_ % K_ : 0;
     zero_counts(nbd_);
@@ -738,9 +774,28 @@ class Engine final : public EngineBase {
           Lm_, items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
       IC_LAUNCHED();
     }
+    const T* fd = dslot(S_);
+    const T* fp = pslot(S_);
+    if (lc_on_) {
+      // lightcone state in order S (tmpd_, tmpp_), its redshift-space
+      // displacement (dbar2_, free in the forward) keys the data order
+      {
+        auto sc = timer_.scope("lc_crossing", P_ * (6.0 * lc_steps_.size() + 15.0) * sizeT());
+        lk::k_lightcone<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+            dslot(S_), pslot(S_), ids(S_), snap_, lcgeo_, rsd(), tmpd_, tmpp_, dbar2_, P_, lp_);
+        IC_LAUNCHED();
+      }
+      zero_counts(nbd_);
+      auto sc = timer_.scope("sort_keys", P_ * (3.0 * sizeT() + 12.0));
+      bk::k_keys<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+          dbar2_, ids(S_), P_, lp_, gdata(), Ld_, bcount_, bkey_, brank_);
+      IC_LAUNCHED();
+      fd = tmpd_;
+      fp = tmpp_;
+    }
     build_order(data_order());
-    scatter(data_order(), state_ptrs(dslot(S_), pslot(S_)), state_mptrs(dsd_, psd_), 6, ids(S_),
-            dids_, dest(S_));
+    scatter(data_order(), state_ptrs(fd, fp), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
+            dest(S_));
     fill(rhod_, T(0), P_);
     auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0));
     bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
@@ -781,6 +836,22 @@ class Engine final : public EngineBase {
     }
     if (tape_forces_) force_mesh(last, gslot(last));
     seg_ = c;
+  }
+
+  // Index of the lightcone snapshot taken at step m, or -1.
+  int snapshot_index(int m) const {
+    for (size_t j = 0; j < lc_steps_.size(); ++j)
+      if (lc_steps_[j] == m) return static_cast<int>(j);
+    return -1;
+  }
+
+  // d_bar += cd sd_j, p_bar += cp sp_j for the particle of each slot of the
+  // order whose lattice ids are id (d_bar may be null).
+  void inject(const unsigned* id, int j, T* db, T cd, T cp) {
+    auto sc = timer_.scope("lc_inject", P_ * ((db ? 12.0 : 6.0) * sizeT() + 4.0));
+    lk::k_inject<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+        id, snapbar_ + (size_t)j * 6 * P_, db, pbar_, cd, cp, P_);
+    IC_LAUNCHED();
   }
 
   bk::Ptrs<T> state_ptrs(const T* d, const T* p) const {
@@ -841,6 +912,16 @@ class Engine final : public EngineBase {
           pbar_);
       IC_LAUNCHED();
     }
+    if (lc_on_) {
+      // lightcone cotangents: final state in place (data order), the other
+      // snapshots into snapbar_ (the final state is still in its slots: no
+      // segment has been replayed yet)
+      auto sc = timer_.scope("lc_adjoint", P_ * (12.0 * lc_steps_.size() + 16.0) * sizeT());
+      lk::k_lightcone_adjoint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+          dslot(S_), pslot(S_), ids(S_), dest(S_), snap_, lcgeo_, rsd(), dbar_, pbar_, snapbar_,
+          P_, lp_);
+      IC_LAUNCHED();
+    }
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
     const double sc_rho = -1.0 / ((double)P_ / (double)M_ * (double)M_);
     for (int n = S_; n >= 0; --n) {
@@ -849,6 +930,13 @@ class Engine final : public EngineBase {
       T* g = gslot(n);
       if (!tape_forces_) force_mesh(n, g);
       const bk::Items it = items(mesh_order(n), ids(n));
+      // a snapshot at step n (d_n, p_n + K2_{n-1} F(d_n)): its d cotangent
+      // joins d_bar; its p cotangent enters the kick at d_n as r = K2 / c_n
+      // times the kicked momentum's (the paint and readout terms scale with
+      // c_n), the rest is added after the step
+      const int js = n < S_ ? snapshot_index(n) : -1;
+      const double r_snap = js >= 0 ? co_.K2[n - 1] / co_.kick[n] : 0.0;
+      if (js >= 0) inject(ids(n + 1), js, dbar_, T(1), static_cast<T>(r_snap));
       fill(gbar_, T(0), 3 * M_);
       {
         auto sc = timer_.scope("cic_paint_vec", P_ * (9.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
@@ -874,6 +962,7 @@ class Engine final : public EngineBase {
       }
       std::swap(dbar_, dbar2_);
       std::swap(pbar_, pbar2_);
+      if (js >= 0) inject(ids(n), js, nullptr, T(0), static_cast<T>(1.0 - r_snap));
     }
     // order 0 to the lattice order of the 2LPT adjoint
     cotangents_back(dest(-1));
@@ -961,6 +1050,14 @@ class Engine final : public EngineBase {
   Coeffs co_;
   int np_, nm_, S_, lp_, lm_, ratio_;
   long long P_, M_;
+  // lightcone: snapshot steps, their states and cotangents, the a(chi) table
+  static constexpr int kLcNodes = 1024;
+  bool lc_on_ = false;
+  std::vector<int> lc_steps_;
+  T* snap_ = nullptr;
+  T* snapbar_ = nullptr;
+  double* lct_ = nullptr;
+  lk::LcGeo lcgeo_{};
   int kpp_ = 0, kpm_ = 0;  // stored half-spectrum row pitches (particle grid, mesh)
   long long Hp_, Hm_;      // stored half-spectrum sizes (padded rows)
   long long Hq_;           // half-spectrum modes of the particle grid, n^2 (n/2+1)

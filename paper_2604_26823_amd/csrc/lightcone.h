@@ -1,0 +1,301 @@
+// Lightcone of the particle output (paper section 2.2.1 item 3, appendix A).
+//
+// Snapshots of the kick-synchronised state are kept at interior steps, in
+// lattice order (6 fields: displacement then momentum).  At the end of the
+// forward model every particle's displacement and momentum are interpolated
+// linearly in a between the snapshots that bracket a, and its crossing scale
+// factor comes from the fixed point a <- A(|x(a) - observer|), started at
+// a_final; A inverts the comoving distance and clamps to the snapshot range.
+// The particle is then painted at x(a_i) with the RSD factor 1/(a_i^2 E(a_i)),
+// carried as the momentum scaled by c(a_i)/c(a_final) so that the data paint
+// and its adjoint stay those of the static model.  All scale-factor
+// arithmetic is FP64; fields are in the working precision.
+//
+// The adjoint recomputes the fixed point per particle and runs it backwards:
+// the cotangents of the final state go back in place (data order), those of
+// the other snapshots to lattice-order buffers, from which the reverse sweep
+// injects them at their steps.
+#pragma once
+
+#include "particles.h"
+
+namespace ic {
+namespace lk {
+
+constexpr int kMaxSnap = 4;
+constexpr int kMaxIter = 16;
+constexpr double kCOverH0 = 2997.92458;  // Mpc/h
+
+// a(chi) as a cubic Hermite table on chi_k = chi_min + k h, k < n (values and
+// slopes da/dchi); a_hi below chi_min, a_lo above chi_max.
+struct LcTable {
+  const double* a;
+  const double* slope;
+  double chi_min, chi_max, h, inv_h;
+  int n;
+  double a_lo, a_hi;
+};
+
+struct LcGeo {
+  double a_snap[kMaxSnap];
+  int J;           // snapshots, the last at a_final
+  int iterations;
+  double om;       // Omega_m of the flat cosmology
+  double c_final;  // RSD factor at a_final
+  LcTable tab;
+};
+
+__device__ __forceinline__ double hubble_E(double a, double om) {
+  return sqrt(om / (a * a * a) + 1.0 - om);
+}
+
+// Crossing scale factor of comoving distance r; unc = r strictly inside
+// the table (the derivative is zero where the result is clamped).
+__device__ __forceinline__ double scale_factor(const LcTable& t, double r, bool& unc) {
+  unc = r > t.chi_min && r < t.chi_max;
+  if (r <= t.chi_min) return t.a_hi;
+  if (r >= t.chi_max) return t.a_lo;
+  const double u = (r - t.chi_min) * t.inv_h;
+  const int k = min(static_cast<int>(u), t.n - 2);
+  const double s = u - k, s1 = 1.0 - s;
+  const double h00 = (1.0 + 2.0 * s) * s1 * s1, h10 = s * s1 * s1;
+  const double h01 = s * s * (3.0 - 2.0 * s), h11 = s * s * (s - 1.0);
+  return h00 * t.a[k] + h10 * t.h * t.slope[k] + h01 * t.a[k + 1] + h11 * t.h * t.slope[k + 1];
+}
+
+// Bracket of a: lower snapshot j (the last with a_snap[j] <= a, at most J-2)
+// and the weight t of snapshot j + 1.
+__device__ __forceinline__ void bracket(const LcGeo& g, double a, int& j, double& t) {
+  j = 0;
+  for (int i = 1; i < g.J - 1; ++i)
+    if (g.a_snap[i] <= a) j = i;
+  t = (a - g.a_snap[j]) / (g.a_snap[j + 1] - g.a_snap[j]);
+}
+
+// One particle's snapshot states (FP64 copies).
+struct Snaps {
+  double d[kMaxSnap][3];
+  double p[kMaxSnap][3];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_snaps(const LcGeo& g, const T* __restrict__ snap,
+                                           const T* __restrict__ dS, const T* __restrict__ pS,
+                                           long long P, long long l, long long a, Snaps& s) {
+  for (int j = 0; j + 1 < g.J; ++j) {
+    const T* b = snap + (long long)j * 6 * P;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      s.d[j][q] = static_cast<double>(b[q * P + l]);
+      s.p[j][q] = static_cast<double>(b[(3 + q) * P + l]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    s.d[g.J - 1][q] = static_cast<double>(dS[q * P + a]);
+    s.p[g.J - 1][q] = static_cast<double>(pS[q * P + a]);
+  }
+}
+
+// Interpolated displacement (as T, the value the line of sight sees) and
+// the slopes d x / d a, d p / d a of the bracket.
+template <typename T>
+__device__ __forceinline__ void interp(const LcGeo& g, const Snaps& s, double a, T d[3],
+                                       double p[3], double dd[3], double dp[3]) {
+  int j;
+  double t;
+  bracket(g, a, j, t);
+  const double span = g.a_snap[j + 1] - g.a_snap[j];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    d[q] = static_cast<T>((1.0 - t) * s.d[j][q] + t * s.d[j + 1][q]);
+    p[q] = (1.0 - t) * s.p[j][q] + t * s.p[j + 1][q];
+    dd[q] = (s.d[j + 1][q] - s.d[j][q]) / span;
+    dp[q] = (s.p[j + 1][q] - s.p[j][q]) / span;
+  }
+}
+
+// Scale factors a^(0) = a_final, a^(k) = A(r(a^(k-1))), k <= iterations;
+// unc[k]: a^(k) was not clamped.
+template <typename T>
+__device__ __forceinline__ void crossing(const LcGeo& g, const pk::Rsd<T>& rsd, const int idx[3],
+                                         const Snaps& s, double* av, bool* unc) {
+  av[0] = g.a_snap[g.J - 1];
+  unc[0] = false;
+  for (int k = 1; k <= g.iterations; ++k) {
+    T d[3], u[3], dist;
+    double p[3], dd[3], dp[3];
+    interp<T>(g, s, av[k - 1], d, p, dd, dp);
+    pk::los(rsd, idx, d, u, dist);
+    av[k] = scale_factor(g.tab, static_cast<double>(dist), unc[k]);
+  }
+}
+
+// Kick-synchronised snapshot of state n (block order, ids = lattice id per
+// slot) into lattice order: d, and p + half_kick F(d).
+template <typename T>
+__global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const T* __restrict__ p,
+                                                  const T* __restrict__ g, long long M,
+                                                  T half_kick, const unsigned* __restrict__ ids,
+                                                  T* __restrict__ snap, long long P, int lp,
+                                                  pk::Grid<T> gm) {
+  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
+       a += (long long)gridDim.x * blockDim.x) {
+    const long long l = ids[a];
+    int idx[3];
+    pk::lattice(l, lp, idx);
+    T dsp[3], mom[3], F[3];
+    pk::load3(d, P, a, dsp);
+    pk::load3(p, P, a, mom);
+    const pk::Stencil<T> s = pk::stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
+    pk::readout3(s, gm.lm, g, M, F);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      snap[q * P + l] = dsp[q];
+      snap[(3 + q) * P + l] = mom[q] + half_kick * F[q];
+    }
+  }
+}
+
+// Lightcone state of every particle of the final order: displacement lcd,
+// momentum scaled to the final RSD factor lcp, and the redshift-space
+// displacement ds (for the data-grid keys).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, const T* __restrict__ pS,
+                                                   const unsigned* __restrict__ ids,
+                                                   const T* __restrict__ snap, LcGeo g,
+                                                   pk::Rsd<T> rsd, T* __restrict__ lcd,
+                                                   T* __restrict__ lcp, T* __restrict__ ds,
+                                                   long long P, int lp) {
+  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
+       a += (long long)gridDim.x * blockDim.x) {
+    const long long l = ids[a];
+    int idx[3];
+    pk::lattice(l, lp, idx);
+    Snaps s;
+    load_snaps<T>(g, snap, dS, pS, P, l, a, s);
+    double av[kMaxIter + 1];
+    bool unc[kMaxIter + 1];
+    crossing<T>(g, rsd, idx, s, av, unc);
+    const double ai = av[g.iterations];
+    T d[3];
+    double p[3], dd[3], dp[3];
+    interp<T>(g, s, ai, d, p, dd, dp);
+    const double k = 1.0 / (ai * ai * hubble_E(ai, g.om) * g.c_final);
+    T pe[3], out[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pe[q] = static_cast<T>(k * p[q]);
+    pk::rsd_shift(rsd, idx, d, pe, out);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      lcd[q * P + a] = d[q];
+      lcp[q * P + a] = pe[q];
+      ds[q * P + a] = out[q];
+    }
+  }
+}
+
+// Adjoint of k_lightcone.  dbar, pbar: cotangents of (lcd, lcp) in the data
+// order on entry (slot dest[a] for final-order slot a), of the final state
+// (d_S, p_S) on exit, in place; snapbar: cotangents of the other snapshots
+// (lattice order, every entry written).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lightcone_adjoint(
+    const T* __restrict__ dS, const T* __restrict__ pS, const unsigned* __restrict__ ids,
+    const unsigned* __restrict__ dest, const T* __restrict__ snap, LcGeo g, pk::Rsd<T> rsd,
+    T* __restrict__ dbar, T* __restrict__ pbar, T* __restrict__ snapbar, long long P, int lp) {
+  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
+       a += (long long)gridDim.x * blockDim.x) {
+    const long long l = ids[a];
+    const long long ad = dest[a];
+    int idx[3];
+    pk::lattice(l, lp, idx);
+    Snaps s;
+    load_snaps<T>(g, snap, dS, pS, P, l, a, s);
+    double av[kMaxIter + 1];
+    bool unc[kMaxIter + 1];
+    crossing<T>(g, rsd, idx, s, av, unc);
+    double sd[kMaxSnap][3], sp[kMaxSnap][3];
+    for (int j = 0; j < g.J; ++j)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sd[j][q] = sp[j][q] = 0.0;
+    const int K = g.iterations;
+    const double ai = av[K];
+    T d[3];
+    double p[3], dd[3], dp[3];
+    interp<T>(g, s, ai, d, p, dd, dp);
+    // lcp = k(a) p with k = c(a) / c_final, c = 1 / (a^2 E)
+    const double E = hubble_E(ai, g.om);
+    const double k = 1.0 / (ai * ai * E * g.c_final);
+    const double dlnE = -1.5 * g.om / (ai * ai * ai * ai * E * E);
+    const double dk = -k * (2.0 / ai + dlnE);
+    double xb[3], pb[3], abar = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      xb[q] = static_cast<double>(dbar[q * P + ad]);
+      const double pe = static_cast<double>(pbar[q * P + ad]);
+      pb[q] = k * pe;
+      abar += dk * p[q] * pe + xb[q] * dd[q] + pb[q] * dp[q];
+    }
+    int j;
+    double t;
+    bracket(g, ai, j, t);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      sd[j][q] += (1.0 - t) * xb[q];
+      sp[j][q] += (1.0 - t) * pb[q];
+      sd[j + 1][q] += t * xb[q];
+      sp[j + 1][q] += t * pb[q];
+    }
+    for (int it = K; it >= 1; --it) {
+      const double ak = av[it];
+      const double rbar = unc[it] ? abar * (-ak * ak * hubble_E(ak, g.om) / kCOverH0) : 0.0;
+      T dk3[3], u[3], dist;
+      double pk3[3], ddk[3], dpk[3];
+      interp<T>(g, s, av[it - 1], dk3, pk3, ddk, dpk);
+      pk::los(rsd, idx, dk3, u, dist);
+      bracket(g, av[it - 1], j, t);
+      abar = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double rd = rbar * static_cast<double>(u[q]);
+        sd[j][q] += (1.0 - t) * rd;
+        sd[j + 1][q] += t * rd;
+        abar += rd * ddk[q];
+      }
+    }
+    for (int jj = 0; jj + 1 < g.J; ++jj) {
+      T* b = snapbar + (long long)jj * 6 * P;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        b[q * P + l] = static_cast<T>(sd[jj][q]);
+        b[(3 + q) * P + l] = static_cast<T>(sp[jj][q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dbar[q * P + ad] = static_cast<T>(sd[g.J - 1][q]);
+      pbar[q * P + ad] = static_cast<T>(sp[g.J - 1][q]);
+    }
+  }
+}
+
+// Snapshot cotangents into the reverse sweep: dbar += cd sd, pbar += cp sp
+// for the particle of each slot (ids: lattice id per slot); dbar may be null.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject(const unsigned* __restrict__ ids,
+                                                const T* __restrict__ sbar, T* __restrict__ dbar,
+                                                T* __restrict__ pbar, T cd, T cp, long long P) {
+  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
+       a += (long long)gridDim.x * blockDim.x) {
+    const long long l = ids[a];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (dbar) dbar[q * P + a] += cd * sbar[q * P + l];
+      pbar[q * P + a] += cp * sbar[(3 + q) * P + l];
+    }
+  }
+}
+
+}  // namespace lk
+}  // namespace ic

@@ -42,6 +42,14 @@ CASES = {
     # the paper-scale geometry (observer inside the 500 Mpc/h box, disk footprint,
     # Planck13, Poisson without prior) on a 32^3 lattice
     "disk32": dict(c=6, n_part=32, n_mesh=32, n_steps=4, galaxies=2e4),
+    # the lightcone (snapshots at a = 0.8, 0.9, 1.0, three fixed-point
+    # iterations) at the paper's 18 steps; with checkpoints and recomputed
+    # forces; with the plane-parallel RSD of c1 (snapshots at steps 3 and 4)
+    "lightcone32": dict(c=6, n_part=32, n_mesh=32, galaxies=2e4, lightcone=(0.8, 0.9, 1.0)),
+    "lightcone32_ckpt4_recompute": dict(c=6, n_part=32, n_mesh=32, galaxies=2e4,
+                                        lightcone=(0.8, 0.9, 1.0), ckpt_every=4,
+                                        tape_forces=0),
+    "lightcone_c1": dict(c=1, lightcone=(0.64, 0.82, 1.0)),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}

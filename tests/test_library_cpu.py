@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.ic_abi_version() == 4
+    assert lib.ic_abi_version() == 5
     p = _lib.IcProblem()
     lib.ic_problem_defaults(ctypes.byref(p))
     assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
@@ -83,6 +83,21 @@ def test_workspace_sizes_and_validation(lib):
     p.loss_kind = 1
     p.bias_k = 0.0
     assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
+    # lightcone: snapshots ascend, sit on interior steps and end at a_final
+    assert p.lc_n == 0 and p.lc_iterations == 3
+    ok = dict(n_steps=18, lightcone=(0.8, 0.9, 1.0))
+    for lc, rc in [((0.8, 0.9, 1.0), 0), ((1.0,), 0), ((0.9, 0.8, 1.0), -1), ((0.8, 0.9), -1),
+                   ((0.82, 1.0), -1), ((0.1, 1.0), -1), ((0.4, 0.6, 0.8, 0.9, 1.0), None)]:
+        cfg = inputs.config(1, **dict(ok, lightcone=lc))
+        if rc is None:
+            with pytest.raises(ValueError):
+                api.make_problem(cfg)
+            continue
+        assert _size(lib, cfg)[0] == rc, lc
+    assert _size(lib, inputs.config(1, **ok, lc_iterations=0))[0] == -1
+    # snapshot states and their cotangents: 2 x 2 x 6 fields of 4 bytes per particle
+    base = _size(lib, inputs.config(1, n_steps=18))[1]
+    assert _size(lib, inputs.config(1, **ok))[1] - base == 2 * 2 * 6 * 4 * 32 ** 3 + 2 * 1024 * 8
 
 
 def test_checkpoints_and_recomputed_forces_shrink_the_workspace(lib):
