@@ -29,7 +29,7 @@
       truth for reference.
 
   python -m paper_2604_26823_amd.studies schedule [--iterations 3600]
-          [--low-iterations 250] [--runs annealed,cold] [--out F]
+          [--low-iterations 250] [--runs annealed,cold] [--lightcone] [--out F]
       The resolution schedule of section 3 at the paper's own scale (c6:
       Planck13, 256^3 in 500 Mpc/h, 18 steps, disk footprint, 1.06e6
       galaxies, Poisson likelihood of the power-law x sigmoid bias, no prior
@@ -40,7 +40,14 @@
       resolution from a random start.  Per run: the loss every 50
       iterations, evaluations, time, moments of the final noise, r_c(k) with
       the truth and the masked correlation of both fields smoothed over 4
-      cells; the losses of s = 0 and of the truth for reference.
+      cells; the losses of s = 0 and of the truth for reference.  With
+      --lightcone, both levels use the paper's snapshots (a = 0.8, 0.9, 1.0).
+
+  python -m paper_2604_26823_amd.studies lightcone [--repeats 3] [--out F]
+      c6 with the paper's snapshots (a = 0.8, 0.9, 1.0; section 2.2.1 item 3,
+      appendix A) against c6 with RSD at a = 1, FP32 and FP64: time per
+      loss+gradient evaluation and of the lightcone kernels, FP32 errors
+      relative to FP64, and how far the lightcone moves the density.
 
 Every output line is one JSON record (also appended to --out)."""
 import argparse
@@ -332,18 +339,13 @@ def ablation(a):
         torch.cuda.empty_cache()
 
 
-def schedule(a):
+def _catalogue_counts(cfg, R, s_true, seed):
+    """Sets cfg["nbar"] so that the truth's rate sums to the catalogue size
+    over the mask (the rate is linear in N-bar) and returns Poisson counts at
+    that N-bar, from this library's FP32 forward model."""
     import torch
 
     from paper_2604_26823_amd.api import Context
-    cfg = inputs.config(6)
-    R = inputs.response_field(cfg)
-    sd = inputs.seeds(6)
-    n = cfg["n_part"]
-    s_true = inputs.white_noise(n, sd["truth"])
-    work = "c6: 256^3, 500 Mpc/h, 18 steps, Planck13, disk footprint, Poisson, 1.06e6 galaxies"
-    # N-bar such that the truth's rate sums to the catalogue size over the
-    # mask (the rate is linear in N-bar), then the counts at that N-bar
     cfg["nbar"] = 1.0
     ctx = Context(cfg, "f32", "cuda:0")
     _observe(ctx, R, np.zeros(R.shape, dtype=np.int32))
@@ -352,7 +354,72 @@ def schedule(a):
     ctx.close()
     del ctx
     cfg["nbar"] = cfg["galaxies"] / float(lam[R >= cfg["r_min"]].sum())
-    counts = inputs.poisson_counts(lam * cfg["nbar"], R, cfg["r_min"], sd["counts"])
+    return inputs.poisson_counts(lam * cfg["nbar"], R, cfg["r_min"], seed)
+
+
+def lightcone(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    snaps = (0.8, 0.9, 1.0)
+    cfg = inputs.config(6, lightcone=snaps)
+    R = inputs.response_field(cfg)
+    sd = inputs.seeds(6)
+    n = cfg["n_part"]
+    s_true = inputs.white_noise(n, sd["truth"])
+    counts = _catalogue_counts(cfg, R, s_true, sd["counts"])
+    static = dict(cfg, lightcone=())
+    work = "c6 with snapshots at a = 0.8, 0.9, 1.0: 256^3, 500 Mpc/h, 18 steps, Poisson"
+    s0 = None
+    out = {}
+    for prec in ("f32", "f64"):
+        for name, c in (("lightcone", cfg), ("static", static)):
+            ctx = Context(c, prec, "cuda:0")
+            _observe(ctx, R, counts)
+            s = torch.tensor(inputs.white_noise(n, sd["start"]), dtype=ctx.dtype,
+                             device=ctx.device)
+            if s0 is None:
+                ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+                s0 = s.double().cpu().numpy()
+            else:
+                s = torch.tensor(s0, dtype=ctx.dtype, device=ctx.device)
+            delta = ctx.forward(s, delta=True)["delta"].double().cpu().numpy()
+            L, g, terms, _ = _timed_eval(ctx, s, None)
+            L, g, terms, ms = _timed_eval(ctx, s, g, repeats=a.repeats)
+            ctx.timing(True)
+            ctx.loss_and_grad(s, g)
+            rows = {r["name"]: r for r in ctx.timing_report()}
+            ctx.timing(False)
+            lc_ms = {k: v["ms"] for k, v in rows.items() if k.startswith("lc_")}
+            out[(prec, name)] = (delta, L, g.double().cpu().numpy())
+            _emit(dict(study="lightcone", workload=work, precision=prec, model=name,
+                       eval_ms=ms, loss=L, chi2=terms["chi2"], lightcone_kernels_ms=lc_ms,
+                       workspace_gb=ctx.ws_bytes / 1e9), a.out)
+            ctx.close()
+            del ctx, s, g
+            torch.cuda.empty_cache()
+    d32, L32, g32 = out[("f32", "lightcone")]
+    d64, L64, g64 = out[("f64", "lightcone")]
+    ds64 = out[("f64", "static")][0]
+    _emit(dict(study="lightcone", workload=work, density_rel_l2_f32=_rel(d32, d64),
+               loss_rel_f32=abs(L32 - L64) / abs(L64), grad_rel_l2_f32=_rel(g32, g64),
+               lightcone_vs_static_density_rel_l2=_rel(d64, ds64),
+               lightcone_vs_static_loss=[L64, out[("f64", "static")][1]]), a.out)
+
+
+def schedule(a):
+    import torch
+
+    from paper_2604_26823_amd.api import Context
+    cfg = inputs.config(6, lightcone=(0.8, 0.9, 1.0) if a.lightcone else ())
+    R = inputs.response_field(cfg)
+    sd = inputs.seeds(6)
+    n = cfg["n_part"]
+    s_true = inputs.white_noise(n, sd["truth"])
+    work = "c6: 256^3, 500 Mpc/h, 18 steps, Planck13, disk footprint, Poisson, 1.06e6 galaxies"
+    if a.lightcone:
+        work += ", lightcone from snapshots at a = 0.8, 0.9, 1.0"
+    counts = _catalogue_counts(cfg, R, s_true, sd["counts"])
     hi = Context(cfg, "f32", "cuda:0")
     _observe(hi, R, counts)
     m = R >= cfg["r_min"]
@@ -427,14 +494,18 @@ def main():
     sc.add_argument("--tape-forces", type=int, default=0)
     sc.add_argument("--profile", action="store_true")
     sc.add_argument("--skip-f64", action="store_true")
+    lcp = sub.add_parser("lightcone")
+    lcp.add_argument("--repeats", type=int, default=3)
     sh = sub.add_parser("schedule")
     sh.add_argument("--iterations", type=int, default=inputs.config(6)["iterations"])
     sh.add_argument("--low-iterations", type=int, default=inputs.config(6)["low_iterations"])
     sh.add_argument("--runs", default="annealed,cold")
-    for p in (pr, sc, ab, sh):
+    sh.add_argument("--lightcone", action="store_true")
+    for p in (pr, sc, ab, sh, lcp):
         p.add_argument("--out", default="")
     a = ap.parse_args()
-    {"precision": precision, "scale": scale, "ablation": ablation, "schedule": schedule}[a.mode](a)
+    {"precision": precision, "scale": scale, "ablation": ablation, "schedule": schedule,
+     "lightcone": lightcone}[a.mode](a)
 
 
 if __name__ == "__main__":

@@ -114,3 +114,67 @@ def test_c4_density_after_two_steps_matches_oracle():
         print("c4 after two steps, %s: sampled density rel L2 %.3e, mean %.2e" % (prec, err, mass))
         assert err <= TOL_DENS[prec]
         assert mass <= (1e-5 if prec == "f32" else 1e-12)
+
+
+def test_c6_lightcone_full_size():
+    """The paper's scale with its lightcone: 256^3 in 500 Mpc/h, 18 steps,
+    snapshots at a = 0.8, 0.9, 1.0, Poisson likelihood without prior.  The
+    FP64 kernels match the oracle to ~1e-13 at 32^3 with the same snapshots;
+    here: a central finite difference of the FP64 loss against its gradient,
+    FP32 against FP64 density and loss, mass conservation, and the
+    lightcone's move of the density against RSD at a = 1 (so the crossing
+    scale factors are not all clamped).  The FP32 gradient is printed, not
+    bounded: at this size it differs from FP64 by ~1e-2 with or without the
+    lightcone, because 1 + delta of nearly empty cells sits near the 1e-6
+    floor of the power law, where FP32 resolves it to ~10%."""
+    require_gpu()
+    cfg = inputs.config(6, lightcone=(0.8, 0.9, 1.0))
+    R = inputs.response_field(cfg)
+    cfg["nbar"] = inputs.nbar_for(cfg, R)
+    sd = inputs.seeds(6)
+    s_true = inputs.white_noise(256, sd["truth"])
+    s0 = inputs.white_noise(256, sd["start"])
+    out = {}
+    counts = None
+    fd = an = None
+    for prec, lc in (("f64", True), ("f32", True), ("f64", False), ("f32", False)):
+        ctx = Context(cfg if lc else dict(cfg, lightcone=()), prec, DEV)
+        try:
+            resp = torch.tensor(R, dtype=ctx.dtype, device=DEV)
+            if counts is None:
+                ctx.set_observation(torch.zeros(ctx.grid, dtype=torch.int32, device=DEV), resp)
+                lam = to_np(ctx.forward(torch.tensor(s_true, dtype=ctx.dtype, device=DEV),
+                                        delta=False, lam=True)["lambda"])
+                counts = inputs.poisson_counts(lam, R, cfg["r_min"], sd["counts"])
+            ctx.set_observation(torch.tensor(counts, dtype=torch.int32, device=DEV), resp)
+            s = torch.tensor(s0, dtype=ctx.dtype, device=DEV)
+            delta = to_np(ctx.forward(s, delta=True)["delta"])
+            L, g, _ = ctx.loss_and_grad(s)
+            out[(prec, lc)] = (delta, L, to_np(g))
+            if prec == "f64" and lc:
+                v = np.random.default_rng(4).standard_normal((256, 256, 256))
+                h = 1e-8
+                Ls = []
+                for sgn in (1, -1):
+                    sv = torch.tensor(s0 + sgn * h * v, dtype=torch.float64, device=DEV)
+                    Ls.append(ctx.forward(sv, delta=False, loss=True)["loss"])
+                fd = (Ls[0] - Ls[1]) / (2 * h)
+                an = float(np.sum(out[(prec, lc)][2] * v))
+        finally:
+            ctx.close()
+            del ctx
+            torch.cuda.empty_cache()
+    print("c6 lightcone FP64: FD %.10e analytic %.10e" % (fd, an))
+    err = {}
+    for lc in (True, False):
+        d64, L64, g64 = out[("f64", lc)]
+        d32, L32, g32 = out[("f32", lc)]
+        err[lc] = (rel_l2(d32, d64), abs(L32 - L64) / abs(L64), rel_l2(g32, g64))
+        print("c6 %s: FP32 vs FP64 density %.3e loss %.3e gradient %.3e"
+              % ("lightcone" if lc else "a = 1", *err[lc]))
+        assert abs(d64.mean()) <= 1e-12 and abs(d32.mean()) <= 1e-5
+    moved = rel_l2(out[("f64", True)][0], out[("f64", False)][0])
+    print("lightcone vs a = 1 density %.3f" % moved)
+    assert abs(fd - an) <= 1e-4 * abs(an)
+    assert moved > 0.05
+    assert err[True][0] <= 5e-5 and err[True][1] <= 1e-6
