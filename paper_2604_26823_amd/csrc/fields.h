@@ -120,11 +120,14 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
       const T r = R[i];
       T lam, dlam = T(0);
       if (o.poisson) {
-        const T u = T(1) + delta > T(kUFloor) ? T(1) + delta : T(kUFloor);
+        // u = 1 + delta is the painted density itself: taken from rho, not
+        // from 1 + (rho - 1), whose cancellation would leave nearly empty
+        // cells (u near the floor) with FP32 rounding of order 1e-7 / u
+        const T u = rho[i] > T(kUFloor) ? rho[i] : T(kUFloor);
         const T sig = T(1) / (T(1) + exp(-o.k * (delta - o.delta_th)));
         const T ua = pow(u, o.alpha);
         lam = o.nbar * r * ua * sig;
-        const T du = T(1) + delta > T(kUFloor) ? o.alpha * ua / u : T(0);
+        const T du = rho[i] > T(kUFloor) ? o.alpha * ua / u : T(0);
         dlam = o.nbar * r * (du * sig + ua * o.k * sig * (T(1) - sig));
       } else {
         lam = o.nbar * r * (T(1) + o.bias * delta);

@@ -125,8 +125,10 @@ def test_c6_lightcone_full_size():
     lightcone's move of the density against RSD at a = 1 (so the crossing
     scale factors are not all clamped).  The FP32 gradient is printed, not
     bounded: at this size it differs from FP64 by ~1e-2 with or without the
-    lightcone, because 1 + delta of nearly empty cells sits near the 1e-6
-    floor of the power law, where FP32 resolves it to ~10%."""
+    lightcone.  Nearly empty cells that hold galaxies get CIC weights of
+    1e-5 cells or less from particles just reaching them, which FP32
+    positions (8e-6 cells of rounding at 250 Mpc/h) fix only to their own
+    size, and the Poisson seed there grows as N alpha / (1 + delta)."""
     require_gpu()
     cfg = inputs.config(6, lightcone=(0.8, 0.9, 1.0))
     R = inputs.response_field(cfg)
