@@ -16,7 +16,8 @@
       projected L-BFGS iterations with rank-order matching every 20.  FP64:
       one evaluation at the same start, compared with FP32.
 
-  python -m paper_2604_26823_amd.studies ablation [--iterations 200] [--out F]
+  python -m paper_2604_26823_amd.studies ablation [--iterations 200]
+          [--objective c2|paper] [--out F]
       The optimiser ablation of appendix B (table 1) on synthetic data of
       the 128^3, 512 Mpc/h radial-selection configuration: the method
       (projected steps, eps_max = 1, rank-order matching every 20) against
@@ -26,7 +27,9 @@
       noise, its cross-correlation coefficient r_c(k) with the truth over the
       box, and the correlation with the truth of both fields smoothed over 4
       cells, on the cells under the mask; the losses of s = 0 and of the
-      truth for reference.
+      truth for reference.  --objective paper: the paper's own objective on
+      its coarse level instead (c6 geometry on 128^3, 18 steps, lightcone,
+      Poisson likelihood without the prior term).
 
   python -m paper_2604_26823_amd.studies schedule [--iterations 3600]
           [--low-iterations 250] [--runs annealed,cold] [--lightcone] [--out F]
@@ -296,22 +299,37 @@ def ablation(a):
     import torch
 
     from paper_2604_26823_amd.api import Context
-    base = inputs.config(2)
+    if a.objective == "paper":
+        # the paper's objective at its coarse level: c6 geometry on 128^3
+        # (3.9 Mpc/h cells), 18 steps, lightcone, Poisson likelihood, no prior
+        cid = 6
+        base = inputs.config(6, n_part=128, n_mesh=128, lightcone=(0.8, 0.9, 1.0))
+        work = ("128^3, 500 Mpc/h, 18 steps, Planck13, disk footprint, lightcone, Poisson "
+                "without prior, 1.06e6 galaxies")
+    else:
+        cid = 2
+        base = inputs.config(2)
+        work = "128^3, 512 Mpc/h, 10 steps, radial selection, ~1e6 galaxies"
     R = inputs.response_field(base)
-    base["nbar"] = inputs.nbar_for(base, R)
-    sd = inputs.seeds(2)
+    sd = inputs.seeds(cid)
     s_true = inputs.white_noise(base["n_part"], sd["truth"])
     s_start = inputs.white_noise(base["n_part"], sd["start"])
-    counts = None
+    if a.objective == "paper":
+        counts = _catalogue_counts(base, R, s_true, sd["counts"])
+    else:
+        base["nbar"] = inputs.nbar_for(base, R)
+        counts = None
     runs = [("method", dict(project_steps=1, eps_max=1.0), True)]
     runs += [("lbfgs_eps%g" % e, dict(project_steps=0, eps_max=e), False)
              for e in (1.0, 0.1, 0.01, 0.001)]
-    work = "128^3, 512 Mpc/h, 10 steps, radial selection, ~1e6 galaxies"
+    first = True
     for name, over, rom in runs:
         cfg = dict(base, **over)
         ctx = Context(cfg, "f32", "cuda:0")
-        if counts is None:
-            counts = _mock_counts(ctx, cfg, R, 2)
+        if first:
+            first = False
+            if counts is None:
+                counts = _mock_counts(ctx, cfg, R, cid)
             _observe(ctx, R, counts)
             zero = torch.zeros(ctx.grid, dtype=ctx.dtype, device=ctx.device)
             L0 = ctx.loss_and_grad(zero)[0]
@@ -487,6 +505,7 @@ def main():
     pr.add_argument("--steps", default="")
     ab = sub.add_parser("ablation")
     ab.add_argument("--iterations", type=int, default=200)
+    ab.add_argument("--objective", choices=["c2", "paper"], default="c2")
     sc = sub.add_parser("scale")
     sc.add_argument("--iterations", type=int, default=50)
     sc.add_argument("--repeats", type=int, default=3)
