@@ -1,6 +1,7 @@
-"""Checks at the 512^3 and 1024^3 force-mesh sizes (GPU): the mesh transforms of
-the 256^3-on-512^3 and 512^3-on-1024^3 problems, and the first PM steps of the
-256^3-on-512^3 problem (20 steps, 1000 Mpc/h) against the oracle.
+"""Checks at the 512^3 and 1024^3 force-mesh sizes and at the paper's own scale
+(GPU): the mesh transforms of the 256^3-on-512^3 and 512^3-on-1024^3 problems,
+the first PM steps of the 256^3-on-512^3 problem (20 steps, 1000 Mpc/h)
+against the oracle, and the 256^3, 18-step problem with the lightcone.
 
 The FP64 oracle cannot run whole evaluations at these sizes in test time, so
 parity uses outputs it computes one by one -- single DFT coefficients summed
