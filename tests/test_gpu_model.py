@@ -50,6 +50,9 @@ CASES = {
                                         lightcone=(0.8, 0.9, 1.0), ckpt_every=4,
                                         tape_forces=0),
     "lightcone_c1": dict(c=1, lightcone=(0.64, 0.82, 1.0)),
+    # four snapshots (the maximum) and a single fixed-point iteration
+    "lightcone32_4snap_iter1": dict(c=6, n_part=32, n_mesh=32, galaxies=2e4,
+                                    lightcone=(0.7, 0.8, 0.9, 1.0), lc_iterations=1),
 }
 TOL_DENS = {"f32": 1e-5, "f64": 1e-10}
 TOL_GRAD = {"f32": 1e-4, "f64": 1e-9}
@@ -159,3 +162,20 @@ def test_checkpointed_gradient_matches_taped_c2(prec):
               % (key[0], key[1], abs(L - L0) / abs(L0), err))
         assert abs(L - L0) <= TOL_CKPT_LOSS[prec] * abs(L0)
         assert err <= TOL_CKPT[prec]
+
+
+def test_single_snapshot_lightcone_is_the_static_model():
+    """A lightcone of the final snapshot alone places every particle at a_final
+    with the final RSD factor: the same density as without the lightcone."""
+    require_gpu()
+    base = case("lightcone32")
+    a = context(dict(base, lightcone=(1.0,)), "f64")
+    b = context(dict(base, lightcone=()), "f64")
+    R = inputs.response_field(base)
+    s0 = inputs.white_noise(32, 11)
+    for ctx in (a, b):
+        ctx.set_observation(torch.zeros(ctx.grid, dtype=torch.int32, device=DEV),
+                            to_dev(R, "f64"))
+    da = to_np(a.forward(to_dev(s0, "f64"))["delta"])
+    db = to_np(b.forward(to_dev(s0, "f64"))["delta"])
+    assert np.max(np.abs(da - db)) <= 1e-12
