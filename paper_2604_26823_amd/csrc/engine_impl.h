@@ -147,13 +147,15 @@ class Engine final : public EngineBase {
     dbg_idx_[1] = c.take<uint32_t>(Hq_);
     dbg_key_[1] = c.take<T>(Hq_);
     dbg_bin_ = c.take<uint32_t>(Hq_);
-    // Lightcone: the snapshots before the last (lattice order, 6 fields) and
+    // Lightcone: the snapshots before the last (each in its step's order, 6
+    // fields), their snapshot slots in the final order,
     // their cotangents, and the inverse comoving-distance table.
     lc_on_ = p.lc_n >= 2;
     if (lc_on_) {
       for (int j = 0; j + 1 < p.lc_n; ++j) lc_steps_.push_back(snapshot_step(p, p.lc_a[j]));
       snap_ = c.take<T>(lc_steps_.size() * 6 * P_);
       snapbar_ = c.take<T>(lc_steps_.size() * 6 * P_);
+      snapinv_ = c.take<uint32_t>(lc_steps_.size() * P_);
       lct_ = c.take<double>(2 * kLcNodes);
     }
     need_ = c.used();
@@ -173,7 +175,8 @@ class Engine final : public EngineBase {
     IC_HIP(hipMemcpyAsync(twp_, tp.data(), tp.size() * sizeof(cx<T>), hipMemcpyHostToDevice, st_));
     IC_HIP(hipMemcpyAsync(twm_, tm.data(), tm.size() * sizeof(cx<T>), hipMemcpyHostToDevice, st_));
     if (lc_on_) {
-      const LightconeTable t = lightcone_table(p.omega_m, p.lc_a[0], p.a_final, kLcNodes);
+      const double a_lo = co_.a[lc_steps_[0]];  // the first snapshot's step
+      const LightconeTable t = lightcone_table(p.omega_m, a_lo, p.a_final, kLcNodes);
       IC_HIP(hipMemcpyAsync(lct_, t.a.data(), kLcNodes * sizeof(double), hipMemcpyHostToDevice,
                             st_));
       IC_HIP(hipMemcpyAsync(lct_ + kLcNodes, t.slope.data(), kLcNodes * sizeof(double),
@@ -187,7 +190,7 @@ class Engine final : public EngineBase {
       g.om = p.omega_m;
       g.c_final = co_.rsd_factor;
       g.tab = lk::LcTable{lct_, lct_ + kLcNodes, t.chi_min, t.chi_max, t.h, 1.0 / t.h,
-                          kLcNodes, p.lc_a[0], p.a_final};
+                          kLcNodes, a_lo, p.a_final};
     }
     IC_HIP(hipStreamSynchronize(st_));
   }
@@ -777,12 +780,23 @@ class Engine final : public EngineBase {
     const T* fd = dslot(S_);
     const T* fp = pslot(S_);
     if (lc_on_) {
-      // lightcone state in order S (tmpd_, tmpp_), its redshift-space
-      // displacement (dbar2_, free in the forward) keys the data order
+      // snapshot slots of the final order, then the lightcone state in order
+      // S (tmpd_, tmpp_); its redshift-space displacement (dbar2_, free in the
+      // forward) keys the data order
+      for (size_t j = 0; j < lc_steps_.size(); ++j) {
+        const int m = lc_steps_[j];
+        auto sc = timer_.scope("lc_slots", P_ * (4.0 * (S_ - m) + 8.0));
+        lk::k_snapshot_slots<<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
+            dest(m), S_ - m, snapinv_ + j * P_, P_);
+        IC_LAUNCHED();
+      }
       {
-        auto sc = timer_.scope("lc_crossing", P_ * (6.0 * lc_steps_.size() + 15.0) * sizeT());
+        auto sc = timer_.scope("lc_crossing",
+                               P_ * ((6.0 * lc_steps_.size() + 15.0) * sizeT() +
+                                     4.0 * (lc_steps_.size() + 1)));
         lk::k_lightcone<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-            dslot(S_), pslot(S_), ids(S_), snap_, lcgeo_, rsd(), tmpd_, tmpp_, dbar2_, P_, lp_);
+            dslot(S_), pslot(S_), ids(S_), snapinv_, snap_, lcgeo_, rsd(), tmpd_, tmpp_, dbar2_,
+            P_, lp_);
         IC_LAUNCHED();
       }
       zero_counts(nbd_);
@@ -845,12 +859,14 @@ class Engine final : public EngineBase {
     return -1;
   }
 
-  // d_bar += cd sd_j, p_bar += cp sp_j for the particle of each slot of the
-  // order whose lattice ids are id (d_bar may be null).
-  void inject(const unsigned* id, int j, T* db, T cd, T cp) {
-    auto sc = timer_.scope("lc_inject", P_ * ((db ? 12.0 : 6.0) * sizeT() + 4.0));
+  // Snapshot j's cotangents (in its step's order m) into the sweep:
+  // d_bar[t] += cd sd_j, p_bar[t] += cp sp_j with t = to[a], the slot in order
+  // m + 1 (to = dest(m)), or t = a in order m itself (to null); d_bar may be
+  // null.
+  void inject(const unsigned* to, int j, T* db, T cd, T cp) {
+    auto sc = timer_.scope("lc_inject", P_ * ((db ? 18.0 : 9.0) * sizeT() + (to ? 4.0 : 0.0)));
     lk::k_inject<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-        id, snapbar_ + (size_t)j * 6 * P_, db, pbar_, cd, cp, P_);
+        to, snapbar_ + (size_t)j * 6 * P_, db, pbar_, cd, cp, P_);
     IC_LAUNCHED();
   }
 
@@ -918,8 +934,8 @@ class Engine final : public EngineBase {
       // segment has been replayed yet)
       auto sc = timer_.scope("lc_adjoint", P_ * (12.0 * lc_steps_.size() + 16.0) * sizeT());
       lk::k_lightcone_adjoint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-          dslot(S_), pslot(S_), ids(S_), dest(S_), snap_, lcgeo_, rsd(), dbar_, pbar_, snapbar_,
-          P_, lp_);
+          dslot(S_), pslot(S_), ids(S_), snapinv_, dest(S_), snap_, lcgeo_, rsd(), dbar_, pbar_,
+          snapbar_, P_, lp_);
       IC_LAUNCHED();
     }
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].
@@ -936,7 +952,7 @@ class Engine final : public EngineBase {
       // c_n), the rest is added after the step
       const int js = n < S_ ? snapshot_index(n) : -1;
       const double r_snap = js >= 0 ? co_.K2[n - 1] / co_.kick[n] : 0.0;
-      if (js >= 0) inject(ids(n + 1), js, dbar_, T(1), static_cast<T>(r_snap));
+      if (js >= 0) inject(dest(n), js, dbar_, T(1), static_cast<T>(r_snap));
       fill(gbar_, T(0), 3 * M_);
       {
         auto sc = timer_.scope("cic_paint_vec", P_ * (9.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
@@ -962,7 +978,7 @@ class Engine final : public EngineBase {
       }
       std::swap(dbar_, dbar2_);
       std::swap(pbar_, pbar2_);
-      if (js >= 0) inject(ids(n), js, nullptr, T(0), static_cast<T>(1.0 - r_snap));
+      if (js >= 0) inject(nullptr, js, nullptr, T(0), static_cast<T>(1.0 - r_snap));
     }
     // order 0 to the lattice order of the 2LPT adjoint
     cotangents_back(dest(-1));
@@ -1056,6 +1072,7 @@ class Engine final : public EngineBase {
   std::vector<int> lc_steps_;
   T* snap_ = nullptr;
   T* snapbar_ = nullptr;
+  uint32_t* snapinv_ = nullptr;  // snapshot slot of every final slot, per snapshot
   double* lct_ = nullptr;
   lk::LcGeo lcgeo_{};
   int kpp_ = 0, kpm_ = 0;  // stored half-spectrum row pitches (particle grid, mesh)

@@ -1,7 +1,10 @@
 // Lightcone of the particle output (paper section 2.2.1 item 3, appendix A).
 //
 // Snapshots of the kick-synchronised state are kept at interior steps, in
-// lattice order (6 fields: displacement then momentum).  At the end of the
+// the block order of their step (6 fields: displacement then momentum);
+// following the recorded sort destinations from that order to the final one
+// gives each final slot its slot in the snapshot (inverse maps built once per
+// forward), so the gathers stay as spatially coherent as the orders are.  At the end of the
 // forward model every particle's displacement and momentum are interpolated
 // linearly in a between the snapshots that bracket a, and its crossing scale
 // factor comes from the fixed point a <- A(|x(a) - observer|), started at
@@ -13,8 +16,8 @@
 //
 // The adjoint recomputes the fixed point per particle and runs it backwards:
 // the cotangents of the final state go back in place (data order), those of
-// the other snapshots to lattice-order buffers, from which the reverse sweep
-// injects them at their steps.
+// the other snapshots to buffers in their snapshot's order, from which the
+// reverse sweep injects them at their steps.
 #pragma once
 
 #include "particles.h"
@@ -78,16 +81,19 @@ struct Snaps {
   double p[kMaxSnap][3];
 };
 
+// Snapshot j of final slot a sits at slot inv[j P + a] of its own order.
 template <typename T>
 __device__ __forceinline__ void load_snaps(const LcGeo& g, const T* __restrict__ snap,
                                            const T* __restrict__ dS, const T* __restrict__ pS,
-                                           long long P, long long l, long long a, Snaps& s) {
+                                           const unsigned* __restrict__ inv, long long P,
+                                           long long a, Snaps& s) {
   for (int j = 0; j + 1 < g.J; ++j) {
     const T* b = snap + (long long)j * 6 * P;
+    const long long sj = inv[(long long)j * P + a];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      s.d[j][q] = static_cast<double>(b[q * P + l]);
-      s.p[j][q] = static_cast<double>(b[(3 + q) * P + l]);
+      s.d[j][q] = static_cast<double>(b[q * P + sj]);
+      s.p[j][q] = static_cast<double>(b[(3 + q) * P + sj]);
     }
   }
 #pragma unroll
@@ -131,8 +137,8 @@ __device__ __forceinline__ void crossing(const LcGeo& g, const pk::Rsd<T>& rsd, 
   }
 }
 
-// Kick-synchronised snapshot of state n (block order, ids = lattice id per
-// slot) into lattice order: d, and p + half_kick F(d).
+// Kick-synchronised snapshot of state n, in its own block order (ids =
+// lattice id per slot): d, and p + half_kick F(d).
 template <typename T>
 __global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const T* __restrict__ p,
                                                   const T* __restrict__ g, long long M,
@@ -141,9 +147,8 @@ __global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const
                                                   pk::Grid<T> gm) {
   for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
        a += (long long)gridDim.x * blockDim.x) {
-    const long long l = ids[a];
     int idx[3];
-    pk::lattice(l, lp, idx);
+    pk::lattice(static_cast<long long>(ids[a]), lp, idx);
     T dsp[3], mom[3], F[3];
     pk::load3(d, P, a, dsp);
     pk::load3(p, P, a, mom);
@@ -151,9 +156,24 @@ __global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const
     pk::readout3(s, gm.lm, g, M, F);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      snap[q * P + l] = dsp[q];
-      snap[(3 + q) * P + l] = mom[q] + half_kick * F[q];
+      snap[q * P + a] = dsp[q];
+      snap[(3 + q) * P + a] = mom[q] + half_kick * F[q];
     }
+  }
+}
+
+// inv[dest_{m+k-1}( ... dest_m(a))] = a for the count orders that follow the
+// snapshot's order m (dest: the first of count destination arrays, P apart):
+// the snapshot slot of every final slot.
+static __global__ __launch_bounds__(256) void k_snapshot_slots(const unsigned* __restrict__ dest,
+                                                               int count,
+                                                               unsigned* __restrict__ inv,
+                                                               long long P) {
+  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
+       a += (long long)gridDim.x * blockDim.x) {
+    long long x = a;
+    for (int k = 0; k < count; ++k) x = dest[(long long)k * P + x];
+    inv[x] = static_cast<unsigned>(a);
   }
 }
 
@@ -163,17 +183,17 @@ __global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const
 template <typename T>
 __global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, const T* __restrict__ pS,
                                                    const unsigned* __restrict__ ids,
+                                                   const unsigned* __restrict__ inv,
                                                    const T* __restrict__ snap, LcGeo g,
                                                    pk::Rsd<T> rsd, T* __restrict__ lcd,
                                                    T* __restrict__ lcp, T* __restrict__ ds,
                                                    long long P, int lp) {
   for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
        a += (long long)gridDim.x * blockDim.x) {
-    const long long l = ids[a];
     int idx[3];
-    pk::lattice(l, lp, idx);
+    pk::lattice(static_cast<long long>(ids[a]), lp, idx);
     Snaps s;
-    load_snaps<T>(g, snap, dS, pS, P, l, a, s);
+    load_snaps<T>(g, snap, dS, pS, inv, P, a, s);
     double av[kMaxIter + 1];
     bool unc[kMaxIter + 1];
     crossing<T>(g, rsd, idx, s, av, unc);
@@ -197,21 +217,21 @@ __global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, con
 
 // Adjoint of k_lightcone.  dbar, pbar: cotangents of (lcd, lcp) in the data
 // order on entry (slot dest[a] for final-order slot a), of the final state
-// (d_S, p_S) on exit, in place; snapbar: cotangents of the other snapshots
-// (lattice order, every entry written).
+// (d_S, p_S) on exit, in place; snapbar: cotangents of the other snapshots,
+// each in its snapshot's order (every entry written).
 template <typename T>
 __global__ __launch_bounds__(256) void k_lightcone_adjoint(
     const T* __restrict__ dS, const T* __restrict__ pS, const unsigned* __restrict__ ids,
-    const unsigned* __restrict__ dest, const T* __restrict__ snap, LcGeo g, pk::Rsd<T> rsd,
-    T* __restrict__ dbar, T* __restrict__ pbar, T* __restrict__ snapbar, long long P, int lp) {
+    const unsigned* __restrict__ inv, const unsigned* __restrict__ dest,
+    const T* __restrict__ snap, LcGeo g, pk::Rsd<T> rsd, T* __restrict__ dbar,
+    T* __restrict__ pbar, T* __restrict__ snapbar, long long P, int lp) {
   for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
        a += (long long)gridDim.x * blockDim.x) {
-    const long long l = ids[a];
     const long long ad = dest[a];
     int idx[3];
-    pk::lattice(l, lp, idx);
+    pk::lattice(static_cast<long long>(ids[a]), lp, idx);
     Snaps s;
-    load_snaps<T>(g, snap, dS, pS, P, l, a, s);
+    load_snaps<T>(g, snap, dS, pS, inv, P, a, s);
     double av[kMaxIter + 1];
     bool unc[kMaxIter + 1];
     crossing<T>(g, rsd, idx, s, av, unc);
@@ -266,10 +286,11 @@ __global__ __launch_bounds__(256) void k_lightcone_adjoint(
     }
     for (int jj = 0; jj + 1 < g.J; ++jj) {
       T* b = snapbar + (long long)jj * 6 * P;
+      const long long sj = inv[(long long)jj * P + a];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        b[q * P + l] = static_cast<T>(sd[jj][q]);
-        b[(3 + q) * P + l] = static_cast<T>(sp[jj][q]);
+        b[q * P + sj] = static_cast<T>(sd[jj][q]);
+        b[(3 + q) * P + sj] = static_cast<T>(sp[jj][q]);
       }
     }
 #pragma unroll
@@ -280,19 +301,21 @@ __global__ __launch_bounds__(256) void k_lightcone_adjoint(
   }
 }
 
-// Snapshot cotangents into the reverse sweep: dbar += cd sd, pbar += cp sp
-// for the particle of each slot (ids: lattice id per slot); dbar may be null.
+// Snapshot cotangents (in the snapshot's order) into the reverse sweep:
+// dbar[t] += cd sd[a], pbar[t] += cp sp[a] with t = dest[a] (the slot in the
+// next order), or t = a when dest is null; dbar may be null.  Targets are
+// distinct, so no atomics.
 template <typename T>
-__global__ __launch_bounds__(256) void k_inject(const unsigned* __restrict__ ids,
+__global__ __launch_bounds__(256) void k_inject(const unsigned* __restrict__ dest,
                                                 const T* __restrict__ sbar, T* __restrict__ dbar,
                                                 T* __restrict__ pbar, T cd, T cp, long long P) {
   for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
        a += (long long)gridDim.x * blockDim.x) {
-    const long long l = ids[a];
+    const long long t = dest ? static_cast<long long>(dest[a]) : a;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      if (dbar) dbar[q * P + a] += cd * sbar[q * P + l];
-      pbar[q * P + a] += cp * sbar[(3 + q) * P + l];
+      if (dbar) dbar[q * P + t] += cd * sbar[q * P + a];
+      pbar[q * P + t] += cp * sbar[(3 + q) * P + a];
     }
   }
 }

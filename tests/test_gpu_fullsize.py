@@ -174,3 +174,35 @@ def test_c3_rank_order_matching_after_optimisation_matches_oracle():
     print("ROM of the optimised field: rel L2 %.3e" % err)
     assert err <= 1e-8
     assert abs(L_gpu - L_orc) <= 1e-6 * abs(L_orc)
+
+
+def _c3_golden():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_density_vjp.txt")
+    rows = np.loadtxt(path, comments="#")
+    kind, idx, val = rows[:, 0].astype(int), rows[:, 1].astype(np.int64), rows[:, 2]
+    return (idx[kind == 0], val[kind == 0]), (idx[kind == 1], val[kind == 1])
+
+
+TOL_C3_DENS = {"f32": 1e-5, "f64": 1e-10}
+TOL_C3_VJP = {"f32": 1e-4, "f64": 1e-9}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_c3_density_and_vjp_match_oracle_samples(prec):
+    """The whole benchmark forward model (10 steps at 256^3) and its adjoint
+    against the FP64 oracle at 4096 sampled cells each
+    (tests/golden/make_c3_golden.py): delta_s at the start field, and J^T w
+    for w the seeded white noise of seed 3001."""
+    require_gpu()
+    c3()
+    (i_d, ref_d), (i_g, ref_g) = _c3_golden()
+    ctx = ctx_for(prec)
+    s = torch.tensor(_STATE["s0"], dtype=ctx.dtype, device=DEV)
+    delta = to_np(ctx.forward(s, delta=True)["delta"]).ravel()
+    w = torch.tensor(inputs.white_noise(256, 3001), dtype=ctx.dtype, device=DEV)
+    sbar = to_np(ctx.vjp(s, w)).ravel()
+    ed, eg = rel_l2(delta[i_d], ref_d), rel_l2(sbar[i_g], ref_g)
+    print("c3 %s against the oracle: sampled density rel L2 %.3e, J^T w %.3e" % (prec, ed, eg))
+    assert ed <= TOL_C3_DENS[prec]
+    assert eg <= TOL_C3_VJP[prec]

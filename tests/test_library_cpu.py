@@ -95,9 +95,11 @@ def test_workspace_sizes_and_validation(lib):
             continue
         assert _size(lib, cfg)[0] == rc, lc
     assert _size(lib, inputs.config(1, **ok, lc_iterations=0))[0] == -1
-    # snapshot states and their cotangents: 2 x 2 x 6 fields of 4 bytes per particle
+    # snapshot states and their cotangents (2 x 2 x 6 fields of 4 bytes per
+    # particle), the snapshot slots of the final order (2 x 4 bytes) and the table
     base = _size(lib, inputs.config(1, n_steps=18))[1]
-    assert _size(lib, inputs.config(1, **ok))[1] - base == 2 * 2 * 6 * 4 * 32 ** 3 + 2 * 1024 * 8
+    assert (_size(lib, inputs.config(1, **ok))[1] - base
+            == (2 * 2 * 6 * 4 + 2 * 4) * 32 ** 3 + 2 * 1024 * 8)
 
 
 def test_checkpoints_and_recomputed_forces_shrink_the_workspace(lib):
