@@ -6,7 +6,7 @@ field: the configuration's seeded white noise; w: seeded white noise of seed
 3001 (both FP32-representable).
 
 Run from the repository root:  python tests/golden/make_c3_golden.py
-(about 15 minutes and 20 GB of host memory).  Calls only the oracle and the
+(about 18 minutes and 20 GB of host memory).  Calls only the oracle and the
 seeded input generators."""
 import os
 import sys
