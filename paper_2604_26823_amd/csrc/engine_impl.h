@@ -107,6 +107,7 @@ class Engine final : public EngineBase {
     rhobar_ = c.take<T>(M_);
     part_ = c.take<double>(3 * kRedBlocks);
     scal_ = c.take<double>(64);
+    lbs_ = c.take<double>(2 * 64);  // two-loop dot products left on the device
     hist_S_ = c.take<T>((size_t)(m + 1) * P_);
     hist_Y_ = c.take<T>((size_t)(m + 1) * P_);
     dir_ = c.take<T>(P_);
@@ -524,6 +525,11 @@ class Engine final : public EngineBase {
     double r = 0;
     reduce_parts(g, 1, &r);
     return (long long)r;
+  }
+
+  void scale(const T* x, double alpha, T* y, long long n) {
+    fk::k_scale<T><<<grid_for(n, kThreads), kThreads, 0, st_>>>(x, static_cast<T>(alpha), y, n);
+    IC_LAUNCHED();
   }
 
   void axpy(const T* a, const T* b, double alpha, T* y, long long n) {
@@ -1092,7 +1098,7 @@ class Engine final : public EngineBase {
   int K_ = 0;          // checkpoint spacing (0: every state kept)
   int seg_ = -1;       // first state of the segment whose states are in their slots
   T *dbar_, *pbar_, *gbar_, *rhobar_;
-  double *part_, *scal_;
+  double *part_, *scal_, *lbs_;
   T *hist_S_, *hist_Y_, *dir_, *strial_, *gtrial_;
   uint64_t *keys_, *keys2_;
   uint32_t *vals_, *vals2_, *small_, *shist_, *binc_;

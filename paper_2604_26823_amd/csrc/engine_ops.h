@@ -161,26 +161,54 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
   const double gnorm = std::sqrt(dot(g, g, P_));
   if (!std::isfinite(gnorm)) throw ApiError(IC_ERR_NONFINITE, "gradient is not finite");
   if (!(gnorm > 0)) throw ApiError(IC_ERR_LINESEARCH, "zero gradient: no descent direction");
-  copy(g, dir_, P_);
   const int h = static_cast<int>(hist_.size());
-  std::vector<double> alpha(h);
-  for (int i = h - 1; i >= 0; --i) {
-    const int sl = hist_[i];
-    alpha[i] = hist_rho_[sl] * dot(hist_S_ + sl * P_, dir_, P_);
-    axpy(dir_, hist_Y_ + sl * P_, -alpha[i], dir_, P_);
-  }
   const double gamma = h ? hist_sy_[hist_.back()] / hist_yy_[hist_.back()] : 1.0 / gnorm;
-  if (gamma != 1.0) axpy(dir_, dir_, gamma - 1.0, dir_, P_);
-  for (int i = 0; i < h; ++i) {
-    const int sl = hist_[i];
-    const double b = hist_rho_[sl] * dot(hist_Y_ + sl * P_, dir_, P_);
-    axpy(dir_, hist_S_ + sl * P_, alpha[i] - b, dir_, P_);
+  double gp;
+  if (h == 0) {
+    scale(g, -gamma, dir_, P_);  // -g / |g|
+    gp = dot(g, dir_, P_);
+  } else {
+    // Fused recursion: every step updates the direction and reduces the dot
+    // product the next step needs into lbs_ on the device, so the host waits
+    // once, for g.p.  A[i] = S_i . q (lbs_[i]), B[i] = Y_i . r (lbs_[64 + i]),
+    // alpha_i = rho_i A[i], beta_i = rho_i B[i] (times gamma for i = 0, whose
+    // dot is taken before the scaling r = gamma q).
+    const unsigned G = grid_for(P_, fk::kRedThreads, kRedBlocks);
+    auto S = [&](int i) { return hist_S_ + hist_[i] * P_; };
+    auto Y = [&](int i) { return hist_Y_ + hist_[i] * P_; };
+    auto rho = [&](int i) { return hist_rho_[hist_[i]]; };
+    auto reduce_to = [&](double* dst) {
+      fk::k_reduce_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, G, 1, dst);
+      IC_LAUNCHED();
+    };
+    fk::k_dot<T><<<G, fk::kRedThreads, 0, st_>>>(S(h - 1), g, part_, P_);
+    IC_LAUNCHED();
+    reduce_to(lbs_ + (h - 1));
+    for (int i = h - 1; i >= 0; --i) {  // q -= alpha_i Y_i
+      const T* in = i == h - 1 ? g : dir_;
+      const T* V = i > 0 ? S(i - 1) : Y(0);
+      fk::k_lbfgs_update<T><<<G, fk::kRedThreads, 0, st_>>>(
+          in, T(1), Y(i), lbs_, i, -1, -rho(i), 0.0, dir_, V, part_, P_);
+      IC_LAUNCHED();
+      reduce_to(i > 0 ? lbs_ + (i - 1) : lbs_ + 64);
+    }
+    for (int i = 0; i < h; ++i) {  // r += (alpha_i - beta_i) S_i; p = -r at the end
+      const bool last = i == h - 1;
+      const T sgn = last ? T(-1) : T(1);
+      const T s_in = sgn * static_cast<T>(i == 0 ? gamma : 1.0);
+      fk::k_lbfgs_update<T><<<G, fk::kRedThreads, 0, st_>>>(
+          dir_, s_in, S(i), lbs_, i, 64 + i, static_cast<double>(sgn) * rho(i),
+          i == 0 ? gamma : 1.0, dir_, last ? g : Y(i + 1), part_, P_);
+      IC_LAUNCHED();
+      if (!last) reduce_to(lbs_ + 64 + i + 1);
+    }
+    double r = 0;
+    reduce_parts(G, 1, &r);
+    gp = r;
   }
-  axpy(dir_, dir_, -2.0, dir_, P_);
-  double gp = dot(g, dir_, P_);
   if (!(gp < 0)) {
     lbfgs_reset();
-    axpy(g, g, -1.0 - 1.0 / gnorm, dir_, P_);
+    scale(g, -1.0 / gnorm, dir_, P_);
     gp = dot(g, dir_, P_);
     inf.restarted = 1;
   }
@@ -197,7 +225,7 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
     if (attempt == 1) {
       if (hist_.empty()) break;
       lbfgs_reset();
-      axpy(g, g, -1.0 - 1.0 / gnorm, dir_, P_);
+      scale(g, -1.0 / gnorm, dir_, P_);
       gp = dot(g, dir_, P_);
       inf.restarted = 1;
     }

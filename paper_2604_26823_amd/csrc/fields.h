@@ -236,6 +236,36 @@ __global__ void k_axpy(const T* a, const T* b, T alpha, T* y, long long n) {
     y[i] = a[i] + alpha * b[i];
 }
 
+// One step of the L-BFGS two-loop recursion: y = s_in x + c X with
+// c = cs (d[ia] - fb d[ib]) from FP64 scalars d left on the device by earlier
+// reductions (ib < 0: no second term), then partial sums of V . y per block
+// (V may be null).  y may alias x.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_lbfgs_update(
+    const T* x, T s_in, const T* __restrict__ X, const double* __restrict__ d, int ia, int ib,
+    double cs, double fb, T* y, const T* __restrict__ V, double* __restrict__ part, long long n) {
+  __shared__ double sh[kRedThreads / 64];
+  const T c = static_cast<T>(cs * (d[ia] - (ib >= 0 ? fb * d[ib] : 0.0)));
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const T v = s_in * x[i] + c * X[i];
+    y[i] = v;
+    if (V) acc += static_cast<double>(V[i]) * static_cast<double>(v);
+  }
+  if (!V) return;
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// y = alpha x.
+template <typename T>
+__global__ void k_scale(const T* __restrict__ x, T alpha, T* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = alpha * x[i];
+}
+
 // y = a - b.
 template <typename T>
 __global__ void k_sub(const T* __restrict__ a, const T* __restrict__ b, T* __restrict__ y,
