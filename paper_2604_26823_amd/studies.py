@@ -17,7 +17,7 @@
       one evaluation at the same start, compared with FP32.
 
   python -m paper_2604_26823_amd.studies ablation [--iterations 200]
-          [--objective c2|paper] [--out F]
+          [--objective c2|paper] [--restarts] [--out F]
       The optimiser ablation of appendix B (table 1) on synthetic data of
       the 128^3, 512 Mpc/h radial-selection configuration: the method
       (projected steps, eps_max = 1, rank-order matching every 20) against
@@ -29,7 +29,9 @@
       cells, on the cells under the mask; the losses of s = 0 and of the
       truth for reference.  --objective paper: the paper's own objective on
       its coarse level instead (c6 geometry on 128^3, 18 steps, lightcone,
-      Poisson likelihood without the prior term).
+      Poisson likelihood without the prior term).  --restarts adds table 1's
+      last rows: plain L-BFGS (eps_max = 1) from the method's checkpoints 5,
+      10 and 15 (after 100, 200, 300 iterations), run to the same total.
 
   python -m paper_2604_26823_amd.studies schedule [--iterations 3600]
           [--low-iterations 250] [--runs annealed,cold] [--lightcone] [--out F]
@@ -269,11 +271,14 @@ def _cross_correlation(a, b, box, nbins=10):
     return out
 
 
-def _optimise(ctx, s, g, L, iterations, rom_every, event0, curve_every, progress=None):
+def _optimise(ctx, s, g, L, iterations, rom_every, event0, curve_every, progress=None,
+              keep=None):
     """Projected (or plain) L-BFGS from (s, g, L) in place; a rank-order
     matching event (real, Fourier, projection, history reset) every
-    rom_every iterations when rom_every > 0.  Returns the loss curve, the
-    evaluation count, a status and the final loss."""
+    rom_every iterations when rom_every > 0.  keep: optional dict whose keys
+    are iteration counts; a copy of s after that many iterations (after the
+    matching event, if one falls there) is stored under each.  Returns the
+    loss curve, the evaluation count, a status and the final loss."""
     curve, evals, status = [[0, L]], 0, "ok"
     for it in range(iterations):
         try:
@@ -292,6 +297,8 @@ def _optimise(ctx, s, g, L, iterations, rom_every, event0, curve_every, progress
             curve.append([it + 1, L])
             if progress:
                 progress(it + 1, L)
+        if keep is not None and it + 1 in keep:
+            keep[it + 1] = s.clone()
     return curve, evals, status, L
 
 
@@ -322,6 +329,11 @@ def ablation(a):
     runs = [("method", dict(project_steps=1, eps_max=1.0), True)]
     runs += [("lbfgs_eps%g" % e, dict(project_steps=0, eps_max=e), False)
              for e in (1.0, 0.1, 0.01, 0.001)]
+    # plain L-BFGS (eps_max = 1) from the method's checkpoints 5, 10 and 15
+    # (one every 20 iterations, right after a matching event), run to the
+    # same total iteration count (table 1: M05L30, M10L30, M15L30)
+    restarts = [k for k in (5, 10, 15) if 20 * k < a.iterations] if a.restarts else []
+    keep = {20 * k: None for k in restarts}
     first = True
     for name, over, rom in runs:
         cfg = dict(base, **over)
@@ -342,19 +354,38 @@ def ablation(a):
         ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
         L, g, _ = ctx.loss_and_grad(s)
         t0 = time.perf_counter()
-        curve, evals, status, L = _optimise(ctx, s, g, L, a.iterations, 20 if rom else 0, 0, 10)
+        curve, evals, status, L = _optimise(ctx, s, g, L, a.iterations, 20 if rom else 0, 0, 10,
+                                            keep=keep if name == "method" else None)
         evals += 1
         torch.cuda.synchronize()
-        final = s.double().cpu().numpy()
-        m = R >= base["r_min"]
-        corr_m = float(np.corrcoef(_smooth(final, 4.0)[m], _smooth(s_true, 4.0)[m])[0, 1])
-        _emit(dict(study="ablation", workload=work, run=name, status=status, final_loss=L,
-                   evaluations=evals, seconds=time.perf_counter() - t0, loss_curve=curve,
-                   white_noise=_white_noise_stats(final), corr_masked=corr_m,
-                   r_c=_cross_correlation(final, s_true, base["box"])), a.out)
+        _ablation_record(a, work, name, base, R, s_true, s, L, status, evals, t0, curve)
         ctx.close()
         del ctx, s, g
         torch.cuda.empty_cache()
+    for k in restarts:
+        ctx = Context(dict(base, project_steps=0, eps_max=1.0), "f32", "cuda:0")
+        _observe(ctx, R, counts)
+        s = keep[20 * k].to(ctx.device)
+        L, g, _ = ctx.loss_and_grad(s)
+        t0 = time.perf_counter()
+        curve, evals, status, L = _optimise(ctx, s, g, L, a.iterations - 20 * k, 0, 0, 10)
+        curve = [[20 * k + i, v] for i, v in curve]
+        torch.cuda.synchronize()
+        _ablation_record(a, work, "M%02dL (plain L-BFGS from checkpoint %d)" % (k, k), base, R,
+                         s_true, s, L, status, evals + 1, t0, curve)
+        ctx.close()
+        del ctx, s, g
+        torch.cuda.empty_cache()
+
+
+def _ablation_record(a, work, name, base, R, s_true, s, L, status, evals, t0, curve):
+    final = s.double().cpu().numpy()
+    m = R >= base["r_min"]
+    corr_m = float(np.corrcoef(_smooth(final, 4.0)[m], _smooth(s_true, 4.0)[m])[0, 1])
+    _emit(dict(study="ablation", workload=work, run=name, status=status, final_loss=L,
+               evaluations=evals, seconds=time.perf_counter() - t0, loss_curve=curve,
+               white_noise=_white_noise_stats(final), corr_masked=corr_m,
+               r_c=_cross_correlation(final, s_true, base["box"])), a.out)
 
 
 def _catalogue_counts(cfg, R, s_true, seed):
@@ -506,6 +537,7 @@ def main():
     ab = sub.add_parser("ablation")
     ab.add_argument("--iterations", type=int, default=200)
     ab.add_argument("--objective", choices=["c2", "paper"], default="c2")
+    ab.add_argument("--restarts", action="store_true")
     sc = sub.add_parser("scale")
     sc.add_argument("--iterations", type=int, default=50)
     sc.add_argument("--repeats", type=int, default=3)
