@@ -208,17 +208,20 @@ int ic_set_observation(ic_ctx* ctx, const int32_t* counts, const void* response)
 
 /* Forward model s -> delta_s (section 2.2.1).  s: device, n_part^3.
  * delta_s, lambda: optional device outputs (n_part^3, NULL to skip).
- * loss: optional host output (needs an observation). */
+ * loss: optional host output (needs an observation).  Returns
+ * IC_ERR_NONFINITE, before any particle moves, when s holds a NaN or inf. */
 int ic_forward(ic_ctx* ctx, const void* s, void* delta_s, void* lambda, double* loss);
 
 /* L(s) = 1/2 chi^2 + 1/2 prior_weight |s|^2 and its gradient (device,
  * n_part^3) by the hand-written adjoint of the forward model.  terms is
- * optional.  Returns IC_ERR_NONFINITE when L or the gradient is not finite. */
+ * optional.  Returns IC_ERR_NONFINITE when s (checked first), L or the
+ * gradient is not finite. */
 int ic_loss_and_grad(ic_ctx* ctx, const void* s, void* grad, double* loss,
                      ic_loss_terms* terms);
 
 /* Vector-Jacobian product s_bar = J^T delta_bar of s -> delta_s (no prior);
- * all device buffers of n_part^3. */
+ * all device buffers of n_part^3.  Returns IC_ERR_NONFINITE when s is not
+ * finite. */
 int ic_vjp(ic_ctx* ctx, const void* s, const void* delta_bar, void* s_bar);
 
 /* In-place rank-order matching and projection of the white noise s
@@ -244,7 +247,7 @@ int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
  * s, grad: device in/out (n_part^3); loss: host in/out; iteration keys the
  * reset draws.  Returns IC_ERR_LINESEARCH when no trial passes or the
  * gradient is zero (s, grad and loss are then unchanged), IC_ERR_NONFINITE
- * when the gradient is not finite. */
+ * when s, the loss or the gradient is not finite. */
 int ic_lbfgs_step(ic_ctx* ctx, void* s, void* grad, double* loss, int64_t iteration,
                   ic_lbfgs_info* info);
 

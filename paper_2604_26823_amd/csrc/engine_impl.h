@@ -213,10 +213,17 @@ class Engine final : public EngineBase {
     resp_ = static_cast<const T*>(response);
   }
 
+  // Non-finite white noise is refused before any particle is moved.
+  void require_finite(const void* x, const char* what) {
+    if (count_nonfinite(static_cast<const T*>(x), P_) > 0)
+      throw ApiError(IC_ERR_NONFINITE, std::string(what) + " is not finite");
+  }
+
   void forward(const void* s, void* delta, void* lambda, double* loss) override {
     if (!s) throw ApiError(IC_ERR_INVALID_ARG, "s is null");
     if (loss && !counts_) throw ApiError(IC_ERR_STATE, "no observation set");
     if (lambda && !resp_) throw ApiError(IC_ERR_STATE, "no observation set");
+    require_finite(s, "s");
     run_forward(static_cast<const T*>(s));
     if (delta || lambda || loss) {
       ic_loss_terms t{};
@@ -229,6 +236,7 @@ class Engine final : public EngineBase {
   void loss_and_grad(const void* s, void* grad, ic_loss_terms* terms) override {
     if (!s || !grad) throw ApiError(IC_ERR_INVALID_ARG, "null buffer");
     if (!counts_) throw ApiError(IC_ERR_STATE, "no observation set");
+    require_finite(s, "s");
     ic_loss_terms t{};
     eval(static_cast<const T*>(s), static_cast<T*>(grad), &t);
     if (terms) *terms = t;
@@ -239,6 +247,7 @@ class Engine final : public EngineBase {
 
   void vjp(const void* s, const void* delta_bar, void* s_bar) override {
     if (!s || !delta_bar || !s_bar) throw ApiError(IC_ERR_INVALID_ARG, "null buffer");
+    require_finite(s, "s");
     run_forward(static_cast<const T*>(s));
     copy(static_cast<const T*>(delta_bar), seed_, P_);
     adjoint(static_cast<T*>(s_bar), nullptr, T(0));

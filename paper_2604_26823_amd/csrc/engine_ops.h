@@ -153,7 +153,9 @@ void Engine<T>::lbfgs_step(void* sv, void* gv, double* loss, int64_t it, ic_lbfg
   if (!counts_) throw ApiError(IC_ERR_STATE, "no observation set");
   T* s = static_cast<T*>(sv);
   T* g = static_cast<T*>(gv);
+  require_finite(s, "s");
   const double L = *loss;
+  if (!std::isfinite(L)) throw ApiError(IC_ERR_NONFINITE, "loss is not finite");
   const int m = prob_.lbfgs_m;
   ic_lbfgs_info inf{};
   // Two-loop recursion: dir = -H g with H0 = gamma I; gamma = S.Y / Y.Y of
