@@ -53,6 +53,9 @@ CASES = {
     # four snapshots (the maximum) and a single fixed-point iteration
     "lightcone32_4snap_iter1": dict(c=6, n_part=32, n_mesh=32, galaxies=2e4,
                                     lightcone=(0.7, 0.8, 0.9, 1.0), lc_iterations=1),
+    # snapshot readouts on a force mesh twice as fine as the particle grid
+    "lightcone32_mesh2": dict(c=6, n_part=32, n_mesh=64, galaxies=2e4,
+                              lightcone=(0.8, 0.9, 1.0)),
     # the lightcone without redshift-space distortions (positions only)
     "lightcone32_norsd": dict(c=6, n_part=32, n_mesh=32, galaxies=2e4, rsd="none",
                               lightcone=(0.8, 0.9, 1.0)),
