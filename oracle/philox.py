@@ -12,16 +12,21 @@ Normal: sqrt(-2 ln u0) cos(2 pi u1) (Box-Muller, first branch).
 Rayleigh with E[a^2] = 1: sqrt(-ln u0).
 
 Streams: 1 = projection reset (sub = line-search trial, event = iteration),
-2 = real-space ROM targets, 3 = Fourier-space ROM targets (sub = k bin).
+2 = real-space ROM targets, 3 = Fourier-space ROM targets (sub = k bin),
+4 = fresh modes of the white-noise upsampling, 5 = Fourier-space ROM targets
+of the real/imaginary-part reading (sub = k bin).
 """
 import numpy as np
 
 __all__ = ["philox4x64", "uniform_pair", "normal", "rayleigh",
-           "STREAM_RESET", "STREAM_ROM_REAL", "STREAM_ROM_FOURIER"]
+           "STREAM_RESET", "STREAM_ROM_REAL", "STREAM_ROM_FOURIER", "STREAM_UPSAMPLE",
+           "STREAM_ROM_FOURIER_REIM"]
 
 STREAM_RESET = 1
 STREAM_ROM_REAL = 2
 STREAM_ROM_FOURIER = 3
+STREAM_UPSAMPLE = 4
+STREAM_ROM_FOURIER_REIM = 5
 
 _M0 = np.uint64(0xD2E7470EE14C6C93)
 _M1 = np.uint64(0xCA5A826395121157)

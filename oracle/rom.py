@@ -21,13 +21,20 @@ Readings taken where the paper is silent:
   b = min(99, floor((|k| - k_min) / dk)), dk = (sqrt(3) pi N / L - k_min)/100.
   The amplitudes |z| are matched to Rayleigh draws (E a^2 = 1), the phases
   are kept, and the conjugate partners are mirrored before the inverse FFT.
+* Fourier space, second reading (rom_fourier_reim): the paper's "matching
+  the Fourier modes" may also mean the real and imaginary parts, which for
+  white noise are independent N(0, 1/2) samples.  Per bin the 2n values
+  Re z_f, Im z_f of its n modes form one set whose canonical order is the
+  element index 2 f + c (c = 0 for Re, 1 for Im, f the flat half-spectrum
+  index), matched to 2n draws of N(0, 1/2); the conjugate partners are
+  mirrored as above.
 """
 import numpy as np
 
 from . import fourier, philox
 
 __all__ = ["descending_order", "match", "rom_real", "fourier_mode_sets",
-           "rom_fourier"]
+           "rom_fourier", "rom_fourier_reim"]
 
 
 def descending_order(values):
@@ -103,3 +110,36 @@ def rom_fourier(s, box, seed, event, k_min=0.1, n_bins=100):
     z[partner[mirror]] = np.conj(z[idx[mirror]])
     out = fourier.irfft3(z.reshape(n, n, n // 2 + 1), n) * norm
     return out, dict(orders=orders, keys=keys)
+
+
+def rom_fourier_reim(s, box, seed, event, k_min=0.1, n_bins=100):
+    """Fourier-space ROM of the real and imaginary parts (second reading).
+
+    Per k bin: the 2n values (Re z_f, Im z_f) of its n matched modes, in the
+    canonical element order 2 f + c, are rank-matched to 2n draws of
+    N(0, 1/2) (Philox stream STREAM_ROM_FOURIER_REIM, sub = bin, j = 0..2n-1,
+    each a standard normal times sqrt(1/2)); conjugate partners mirrored."""
+    s = np.asarray(s, dtype=np.float64)
+    n = s.shape[0]
+    norm = n ** 1.5
+    z = (fourier.rfft3(s) / norm).reshape(-1)
+    idx, bins, partner = fourier_mode_sets(n, box, k_min, n_bins)
+    orders, keys, elements = {}, {}, {}
+    for b in range(n_bins):
+        sel = np.nonzero(bins == b)[0]
+        if sel.size == 0:
+            continue
+        zz = z[idx[sel]]
+        v = np.empty(2 * sel.size)
+        v[0::2], v[1::2] = zz.real, zz.imag
+        targets = philox.normal(np.arange(2 * sel.size, dtype=np.uint64), b,
+                                philox.STREAM_ROM_FOURIER_REIM, event, seed) * np.sqrt(0.5)
+        new, o = match(v, targets)
+        z[idx[sel]] = new[0::2] + 1j * new[1::2]
+        e = np.empty(2 * sel.size, dtype=np.int64)
+        e[0::2], e[1::2] = 2 * idx[sel], 2 * idx[sel] + 1
+        orders[b], keys[b], elements[b] = o, v, e
+    mirror = partner >= 0
+    z[partner[mirror]] = np.conj(z[idx[mirror]])
+    out = fourier.irfft3(z.reshape(n, n, n // 2 + 1), n) * norm
+    return out, dict(orders=orders, keys=keys, elements=elements)

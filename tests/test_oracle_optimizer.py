@@ -285,3 +285,47 @@ def test_plain_lbfgs_reaches_the_minimiser_of_a_quadratic():
     assert np.linalg.norm(g) < 1e-6
     ref = np.linalg.solve(A, b)
     assert np.max(np.abs(x - ref)) <= 1e-6
+
+
+def test_rom_fourier_reim_properties():
+    """Second reading of the Fourier-space matching (section 2.3.2): per k bin
+    the real and imaginary parts of the matched modes are one set of 2n
+    values matched to 2n draws of N(0, 1/2).  Pins: after the inverse and a
+    fresh forward transform each bin's Re/Im multiset is the sorted draws,
+    their ranks are the input's ranks (brute-force O(n^2) ranks on every
+    bin), modes outside the matched set and their partners are untouched, and
+    the draws have the variance 1/2 of a white-noise mode's parts."""
+    n, L = 16, 128.0
+    s = np.random.default_rng(26).standard_normal((n, n, n))
+    out, info = rom.rom_fourier_reim(s, L, 7, 2)
+    assert out.dtype == np.float64 and out.shape == s.shape
+    z0 = (fourier.rfft3(s) / n ** 1.5).reshape(-1)
+    z1 = (fourier.rfft3(out) / n ** 1.5).reshape(-1)
+    idx, bins, partner = rom.fourier_mode_sets(n, L)
+    touched = np.zeros(z0.size, bool)
+    touched[idx] = True
+    touched[partner[partner >= 0]] = True
+    assert np.max(np.abs(z1[~touched] - z0[~touched])) <= 1e-12
+    nb = 0
+    for b in range(100):
+        sel = np.nonzero(bins == b)[0]
+        if sel.size == 0:
+            continue
+        nb += 1
+        old = np.empty(2 * sel.size)
+        old[0::2], old[1::2] = z0[idx[sel]].real, z0[idx[sel]].imag
+        new = np.empty(2 * sel.size)
+        new[0::2], new[1::2] = z1[idx[sel]].real, z1[idx[sel]].imag
+        t = philox.normal(np.arange(2 * sel.size, dtype=np.uint64), b,
+                          philox.STREAM_ROM_FOURIER_REIM, 2, 7) * np.sqrt(0.5)
+        assert np.allclose(np.sort(new), np.sort(t), rtol=0, atol=1e-12)
+        ranks = np.array(brute_ranks(list(old)))
+        assert np.allclose(new, np.sort(t)[::-1][ranks], rtol=0, atol=1e-12)
+        assert np.array_equal(info["elements"][b][0::2], 2 * idx[sel])
+    assert nb > 50
+    # conjugate partners hold the conjugate of their matched mode
+    m = partner >= 0
+    assert np.max(np.abs(z1[partner[m]] - np.conj(z1[idx[m]]))) <= 1e-12
+    d = philox.normal(np.arange(400000, dtype=np.uint64), 3, philox.STREAM_ROM_FOURIER_REIM,
+                      1, 9) * np.sqrt(0.5)
+    assert abs(d.mean()) <= 5e-3 and abs(d.var() - 0.5) <= 5e-3
