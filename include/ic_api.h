@@ -65,6 +65,11 @@ extern "C" {
 #define IC_PROJECT 1u
 #define IC_ROM_REAL 2u
 #define IC_ROM_FOURIER 4u
+/* Second reading of the Fourier-space matching (section 2.3.2, "matching
+ * the Fourier modes"): per k bin, the real and imaginary parts of the n
+ * matched modes form one set of 2n values matched to 2n draws of N(0, 1/2)
+ * instead of the amplitudes to Rayleigh draws.  Excludes IC_ROM_FOURIER. */
+#define IC_ROM_FOURIER_REIM 8u
 
 /* Method parameters the paper fixes (section 2.3.1: reset threshold;
  * section 2.3.2: 100 equal-width k bins, modes below k = 0.1 h/Mpc left
@@ -226,11 +231,15 @@ int ic_vjp(ic_ctx* ctx, const void* s, const void* delta_bar, void* s_bar);
 
 /* In-place rank-order matching and projection of the white noise s
  * (sections 2.3.1-2.3.2), in the order real-space matching on M = 1 cells,
- * Fourier-space matching of |z| per k bin, projection P (z-score and reset
- * of |s| > s_th, repeated until a pass resets nothing, so the result has
- * mean 0, std 1 and no extremes); flags selects the parts.  event keys the
- * random draws (reset draws also use trial).  info is optional.  A
- * rank-order pass fails with IC_ERR_NONFINITE on NaN. */
+ * Fourier-space matching per k bin (of |z| to Rayleigh draws, phases kept,
+ * with IC_ROM_FOURIER; of Re z and Im z together to N(0, 1/2) draws with
+ * IC_ROM_FOURIER_REIM), projection P (z-score and reset of |s| > s_th,
+ * repeated until a pass resets nothing, so the result has mean 0, std 1
+ * and no extremes); flags selects the parts.  event keys the random draws
+ * (reset draws also use trial).  info is optional; its n_fourier counts
+ * matched modes under either reading.  A rank-order pass fails with
+ * IC_ERR_NONFINITE on NaN; both Fourier flags together give
+ * IC_ERR_INVALID_ARG. */
 int ic_project_rankmatch(ic_ctx* ctx, void* s, uint32_t flags, uint64_t event,
                          int32_t trial, ic_rom_info* info);
 

@@ -66,9 +66,11 @@ int ic_op_philox(ic_ctx* ctx, int kind, uint64_t sub, uint64_t stream, uint64_t 
 
 /* Order of the last rank-order matching pass (space 0 = real, 1 = Fourier):
  * for each matched element in descending-rank order, its flat index (into
- * the field, or into the half spectrum), the key it was ranked by and, in
- * Fourier space, its k bin.  Host buffers of capacity cap; *n receives the
- * element count.  Needs a prior ic_project_rankmatch on this context. */
+ * the field, or into the half spectrum; under IC_ROM_FOURIER_REIM the
+ * element index 2 f + c of part c (0 = Re, 1 = Im) of half-spectrum mode f),
+ * the key it was ranked by and, in Fourier space, its k bin.  Host buffers
+ * of capacity cap; *n receives the element count.  Needs a prior
+ * ic_project_rankmatch on this context. */
 int ic_debug_rom_order(ic_ctx* ctx, int space, int32_t* idx, void* keys, int32_t* bins,
                        int64_t cap, int64_t* n);
 

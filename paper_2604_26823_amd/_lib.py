@@ -16,7 +16,7 @@ IC_ERR = {
 }
 IC_F32, IC_F64 = 0, 1
 IC_RSD = {"none": 0, "z": 1, "radial": 2}
-IC_PROJECT, IC_ROM_REAL, IC_ROM_FOURIER = 1, 2, 4
+IC_PROJECT, IC_ROM_REAL, IC_ROM_FOURIER, IC_ROM_FOURIER_REIM = 1, 2, 4, 8
 IC_GRID_PART, IC_GRID_MESH = 0, 1
 IC_MULT_WHITE, IC_MULT_GRAD, IC_MULT_HESS = 1, 2, 4
 

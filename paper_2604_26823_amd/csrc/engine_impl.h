@@ -80,7 +80,10 @@ class Engine final : public EngineBase {
     mid_ = bk::max_items(Ld_, P_);
     const int m = std::max(1, p.lbfgs_m);
     wtab_len_ = 3 * (np_ / 2) * (np_ / 2) + 1;
-    sort_blocks_ = (P_ + sk::kTile - 1) / sk::kTile;
+    // sort length of rank-order matching: the field, or the 2 n^2 (n/2+1)
+    // real and imaginary parts of the half spectrum (IC_ROM_FOURIER_REIM)
+    rom_len_ = std::max(P_, 2 * Hq_);
+    sort_blocks_ = (rom_len_ + sk::kTile - 1) / sk::kTile;
 
     Carver c(ws);
     twp_ = c.take<cx<T>>(np_);
@@ -113,14 +116,14 @@ class Engine final : public EngineBase {
     dir_ = c.take<T>(P_);
     strial_ = c.take<T>(P_);
     gtrial_ = c.take<T>(P_);
-    keys_ = c.take<uint64_t>(P_);
-    keys2_ = c.take<uint64_t>(P_);
-    vals_ = c.take<uint32_t>(P_);
-    vals2_ = c.take<uint32_t>(P_);
-    small_ = c.take<uint32_t>(P_);
+    keys_ = c.take<uint64_t>(rom_len_);
+    keys2_ = c.take<uint64_t>(rom_len_);
+    vals_ = c.take<uint32_t>(rom_len_);
+    vals2_ = c.take<uint32_t>(rom_len_);
+    small_ = c.take<uint32_t>(rom_len_);
     shist_ = c.take<uint32_t>(sk::kDigits * sort_blocks_);
-    vbuf_ = c.take<T>(P_);
-    tbuf_ = c.take<T>(P_);
+    vbuf_ = c.take<T>(rom_len_);
+    tbuf_ = c.take<T>(rom_len_);
     binc_ = c.take<uint32_t>(256);
     // Block orders of the particles: one per mesh state d_0..d_S, one on the
     // data grid; ids and dest per order (see blocks.h).
@@ -145,9 +148,9 @@ class Engine final : public EngineBase {
     pbar2_ = c.take<T>(3 * P_);
     dbg_idx_[0] = c.take<uint32_t>(P_);
     dbg_key_[0] = c.take<T>(P_);
-    dbg_idx_[1] = c.take<uint32_t>(Hq_);
-    dbg_key_[1] = c.take<T>(Hq_);
-    dbg_bin_ = c.take<uint32_t>(Hq_);
+    dbg_idx_[1] = c.take<uint32_t>(2 * Hq_);
+    dbg_key_[1] = c.take<T>(2 * Hq_);
+    dbg_bin_ = c.take<uint32_t>(2 * Hq_);
     // Lightcone: the snapshots before the last (each in its step's order, 6
     // fields), their snapshot slots in the final order,
     // their cotangents, and the inverse comoving-distance table.
@@ -258,14 +261,18 @@ class Engine final : public EngineBase {
     if (!sv) throw ApiError(IC_ERR_INVALID_ARG, "s is null");
     T* s = static_cast<T*>(sv);
     ic_rom_info inf{};
-    if (flags & (IC_ROM_REAL | IC_ROM_FOURIER)) {
+    if (flags & (IC_ROM_REAL | IC_ROM_FOURIER | IC_ROM_FOURIER_REIM)) {
       if (count_nonfinite(s, P_) > 0) throw ApiError(IC_ERR_NONFINITE, "non-finite input to matching");
     }
     if (flags & IC_ROM_REAL) {
       if (!resp_) throw ApiError(IC_ERR_STATE, "real-space matching needs the response field");
       inf.n_real = rom_real(s, event);
     }
-    if (flags & IC_ROM_FOURIER) inf.n_fourier = rom_fourier(s, event, &inf.bins_used);
+    if ((flags & IC_ROM_FOURIER) && (flags & IC_ROM_FOURIER_REIM))
+      throw ApiError(IC_ERR_INVALID_ARG,
+                     "IC_ROM_FOURIER and IC_ROM_FOURIER_REIM are alternative readings");
+    if (flags & (IC_ROM_FOURIER | IC_ROM_FOURIER_REIM))
+      inf.n_fourier = rom_fourier(s, event, &inf.bins_used, (flags & IC_ROM_FOURIER_REIM) != 0);
     if (flags & IC_PROJECT) inf.resets = project(s, s, (uint64_t)trial, event);
     if (info) *info = inf;
   }
@@ -1073,7 +1080,7 @@ class Engine final : public EngineBase {
 
   // ------------------------------------------------------------------ ROM
   long long rom_real(T* s, uint64_t event);
-  long long rom_fourier(T* s, uint64_t event, int32_t* bins_used);
+  long long rom_fourier(T* s, uint64_t event, int32_t* bins_used, bool reim);
 
   // members
   ic_problem prob_;
@@ -1095,6 +1102,7 @@ class Engine final : public EngineBase {
   long long Hq_;           // half-spectrum modes of the particle grid, n^2 (n/2+1)
   bool tape_forces_;
   int wtab_len_;
+  long long rom_len_;
   long long sort_blocks_;
   size_t need_ = 0;
   long long pool_len_ = 0;

@@ -69,12 +69,15 @@ long long Engine<T>::rom_real(T* s, uint64_t event) {
   return n;
 }
 
-// Fourier space: z = rfft(s) / N^(3/2); independent modes with |k| >= k_min,
-// per equal-width k bin, ranked by |z| (ties by half-spectrum index), get the
-// sorted Rayleigh targets of their bin; phases are kept and conjugate
-// partners mirrored before the inverse transform.
+// Fourier space: z = rfft(s) / N^(3/2); independent modes with |k| >= k_min
+// are matched per equal-width k bin.  Amplitude reading: ranked by |z| (ties
+// by half-spectrum index), they get the sorted Rayleigh targets of their
+// bin, phases kept.  Real/imaginary-part reading (reim): the 2n parts of a
+// bin's n modes, ranked by value (ties by element index 2 f + c), get the
+// sorted N(0, 1/2) targets of their bin.  Conjugate partners are mirrored
+// before the inverse transform.  Returns the number of matched modes.
 template <typename T>
-long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
+long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used, bool reim) {
   auto f = fa(0);
   cx<T>* Z = pool_;
   fft_r2c_z<T>(f, s, T(1), nullptr, T(0), Z);
@@ -86,19 +89,26 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
   const double kf = 2.0 * 3.14159265358979323846 / prob_.box;
   const double kmax = std::sqrt(3.0) * 3.14159265358979323846 * np_ / prob_.box;
   const double dk = (kmax - prob_.rom_kmin) / nbins;
+  const long long E = reim ? 2 * Hq_ : Hq_;  // ranked elements
   const unsigned G = grid_for(Hq_, kThreads);
+  const unsigned GE = grid_for(E, kThreads);
   const int vbits = 8 * sizeof(T);
-  rk::k_mode_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, kpp_, static_cast<T>(1.0 / n3h), kf,
-                                              prob_.rom_kmin, dk, nbins, vbuf_, keys_, vals_,
-                                              small_, Hq_);
+  if (reim)
+    rk::k_part_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, kpp_, static_cast<T>(1.0 / n3h), kf,
+                                                prob_.rom_kmin, dk, nbins, vbuf_, keys_, vals_,
+                                                small_, Hq_);
+  else
+    rk::k_mode_keys<T><<<G, kThreads, 0, st_>>>(Z, np_, kpp_, static_cast<T>(1.0 / n3h), kf,
+                                                prob_.rom_kmin, dk, nbins, vbuf_, keys_, vals_,
+                                                small_, Hq_);
   IC_LAUNCHED();
-  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hq_, vbits, st_);
-  sk::k_gather_u32_key<<<G, kThreads, 0, st_>>>(small_, vals_, keys_, Hq_);
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, E, vbits, st_);
+  sk::k_gather_u32_key<<<GE, kThreads, 0, st_>>>(small_, vals_, keys_, E);
   IC_LAUNCHED();
-  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, Hq_, 8, st_);
+  radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, E, 8, st_);
   ek::k_fill_u32<<<1, 256, 0, st_>>>(binc_, 0u, 256);
   IC_LAUNCHED();
-  rk::k_bin_ends<<<G, kThreads, 0, st_>>>(keys_, binc_, Hq_);
+  rk::k_bin_ends<<<GE, kThreads, 0, st_>>>(keys_, binc_, E);
   IC_LAUNCHED();
   std::vector<uint32_t>& counts = bin_count_;
   IC_HIP(hipMemcpyAsync(counts.data(), binc_, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
@@ -130,21 +140,32 @@ long long Engine<T>::rom_fourier(T* s, uint64_t event, int32_t* bins_used) {
     IC_LAUNCHED();
     rk::k_gather<T><<<Gn, kThreads, 0, st_>>>(vbuf_, dbg_idx_[1], dbg_key_[1], n);
     IC_LAUNCHED();
-    rk::k_fourier_targets<T><<<Gn, kThreads, 0, st_>>>(keys_, binc_ + 128, event, prob_.seed,
-                                                       tbuf_, keys_, vals_, small_, n);
+    // Rayleigh draws (stream 3) for amplitudes; N(0, 1/2) draws (stream 5)
+    // for the parts
+    rk::k_fourier_targets<T><<<Gn, kThreads, 0, st_>>>(
+        keys_, binc_ + 128, reim ? 0 : 1, reim ? 5 : 3, reim ? std::sqrt(0.5) : 1.0, event,
+        prob_.seed, tbuf_, keys_, vals_, small_, n);
     IC_LAUNCHED();
     radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, vbits, st_);
     sk::k_gather_u32_key<<<Gn, kThreads, 0, st_>>>(small_, vals_, keys_, n);
     IC_LAUNCHED();
     radix_sort_pairs(keys_, vals_, keys2_, vals2_, shist_, n, 8, st_);
-    rk::k_fourier_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, kpp_, dbg_idx_[1], tbuf_,
-                                                       vals_, static_cast<T>(n3h), n);
-    IC_LAUNCHED();
+    if (reim) {
+      rk::k_part_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, kpp_, dbg_idx_[1], tbuf_, vals_,
+                                                      static_cast<T>(n3h), n);
+      IC_LAUNCHED();
+      rk::k_part_mirror<T><<<Gn, kThreads, 0, st_>>>(Z, np_, kpp_, dbg_idx_[1], n);
+      IC_LAUNCHED();
+    } else {
+      rk::k_fourier_scatter<T><<<Gn, kThreads, 0, st_>>>(Z, np_, kpp_, dbg_idx_[1], tbuf_,
+                                                         vals_, static_cast<T>(n3h), n);
+      IC_LAUNCHED();
+    }
   }
   fft_x<T>(f, Z, Z, false, static_cast<T>(1.0 / (double)P_));
   fft_y<T>(f, Z, false);
   fft_c2r_z<T>(f, Z, s, T(1), nullptr, T(0));
-  return n;
+  return reim ? n / 2 : n;
 }
 
 template <typename T>

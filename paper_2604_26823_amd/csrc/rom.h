@@ -58,6 +58,28 @@ __global__ void k_scatter_sorted(T* __restrict__ s, const uint32_t* __restrict__
     s[idx[j]] = tau[order[j]];
 }
 
+// Bin of half-spectrum mode f (kz, ky, kx its wave indices): the k bin of
+// an independent mode with |k| >= k_min, else 255.
+__device__ __forceinline__ uint32_t mode_bin(long long f, int n, double kf, double kmin,
+                                             double dk, int nbins) {
+  const int K = n / 2 + 1;
+  const int kz = static_cast<int>(f % K);
+  const long long r = f / K;
+  const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
+  bool independent = true;
+  if (kz == 0 || kz == n / 2) {
+    const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
+    const long long conj = ((long long)cx_ * n + cy) * K + kz;
+    independent = f < conj;
+  }
+  const int ix = kx < n / 2 ? kx : kx - n;
+  const int iy = ky < n / 2 ? ky : ky - n;
+  const double k = kf * sqrt((double)(ix * ix + iy * iy + kz * kz));
+  if (!independent || k < kmin) return 255u;
+  const int b = static_cast<int>(floor((k - kmin) / dk));
+  return static_cast<uint32_t>(b < nbins - 1 ? b : nbins - 1);
+}
+
 // Fourier space: for every half-spectrum mode f = (kx n + ky)(n/2+1) + kz
 // (stored at (kx n + ky) kp + kz), amplitude |z| = |Z_f| * scale, descending
 // key, and second key = bin for matched modes (independent, |k| >= k_min)
@@ -73,27 +95,39 @@ __global__ void k_mode_keys(const cx<T>* __restrict__ Z, int n, int kp, T scale,
        f += (long long)gridDim.x * blockDim.x) {
     const int kz = static_cast<int>(f % K);
     const long long r = f / K;
-    const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
     const cx<T> z = Z[r * kp + kz];
     const T a = sqrt(z.x * z.x + z.y * z.y) * scale;
     amp[f] = a;
     keys[f] = sk::descending_key<T>(a);
     vals[f] = static_cast<uint32_t>(f);
-    bool independent = true;
-    if (kz == 0 || kz == n / 2) {
-      const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
-      const long long conj = ((long long)cx_ * n + cy) * K + kz;
-      independent = f < conj;
+    second[f] = mode_bin(f, n, kf, kmin, dk, nbins);
+  }
+}
+
+// Real/imaginary-part reading: element e = 2 f + c holds part c (0 = Re,
+// 1 = Im) of mode f times scale, with its descending key and the bin of f
+// as second key.
+template <typename T>
+__global__ void k_part_keys(const cx<T>* __restrict__ Z, int n, int kp, T scale, double kf,
+                            double kmin, double dk, int nbins, T* __restrict__ val,
+                            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            uint32_t* __restrict__ second, long long H) {
+  const int K = n / 2 + 1;
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < H;
+       f += (long long)gridDim.x * blockDim.x) {
+    const int kz = static_cast<int>(f % K);
+    const long long r = f / K;
+    const cx<T> z = Z[r * kp + kz];
+    const uint32_t bin = mode_bin(f, n, kf, kmin, dk, nbins);
+    const T v[2] = {z.x * scale, z.y * scale};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const long long e = 2 * f + c;
+      val[e] = v[c];
+      keys[e] = sk::descending_key<T>(v[c]);
+      vals[e] = static_cast<uint32_t>(e);
+      second[e] = bin;
     }
-    const int ix = kx < n / 2 ? kx : kx - n;
-    const int iy = ky < n / 2 ? ky : ky - n;
-    const double k = kf * sqrt((double)(ix * ix + iy * iy + kz * kz));
-    uint32_t bin = 255u;
-    if (independent && k >= kmin) {
-      int b = static_cast<int>(floor((k - kmin) / dk));
-      bin = static_cast<uint32_t>(b < nbins - 1 ? b : nbins - 1);
-    }
-    second[f] = bin;
   }
 }
 
@@ -111,11 +145,13 @@ static __global__ void k_bin_ends(const uint64_t* __restrict__ bins, uint32_t* _
   }
 }
 
-// Rayleigh target of sorted position i: bin b = bins[i], index within the
-// bin j = i - start[b]; second key of the target sort is the bin.
+// Target of sorted position i: bin b = bins[i], index within the bin
+// j = i - start[b], draw kind (1 = Rayleigh, 0 = normal) of the given
+// stream times mult; second key of the target sort is the bin.
 template <typename T>
 __global__ void k_fourier_targets(const uint64_t* __restrict__ bins,
-                                  const uint32_t* __restrict__ start, uint64_t event,
+                                  const uint32_t* __restrict__ start, int kind, uint64_t stream,
+                                  double mult, uint64_t event,
                                   uint64_t seed, T* __restrict__ tau,
                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                   uint32_t* __restrict__ second, long long n) {
@@ -123,7 +159,7 @@ __global__ void k_fourier_targets(const uint64_t* __restrict__ bins,
        i += (long long)gridDim.x * blockDim.x) {
     const uint32_t b = static_cast<uint32_t>(bins[i]);
     const uint64_t j = (uint64_t)(i - start[b]);
-    const T v = static_cast<T>(fk::philox_draw(1, j, b, 3, event, seed));
+    const T v = static_cast<T>(fk::philox_draw(kind, j, b, stream, event, seed) * mult);
     tau[i] = v;
     keys[i] = sk::descending_key<T>(v);
     vals[i] = static_cast<uint32_t>(i);
@@ -155,6 +191,44 @@ __global__ void k_fourier_scatter(cx<T>* __restrict__ Z, int n, int kp,
       const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
       Z[((long long)cx_ * n + cy) * kp + kz] = mkc<T>(v.x, -v.y);
     }
+  }
+}
+
+// Real/imaginary-part reading: part c of mode f (element idx[i] = 2 f + c)
+// <- tau[order[i]] * unscale.
+template <typename T>
+__global__ void k_part_scatter(cx<T>* __restrict__ Z, int n, int kp,
+                               const uint32_t* __restrict__ idx, const T* __restrict__ tau,
+                               const uint32_t* __restrict__ order, T unscale, long long cnt) {
+  const int K = n / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long e = idx[i];
+    const long long f = e >> 1;
+    const int kz = static_cast<int>(f % K);
+    T* z = reinterpret_cast<T*>(Z + (f / K) * kp + kz);
+    z[e & 1] = tau[order[i]] * unscale;
+  }
+}
+
+// After k_part_scatter: every matched mode of the kz = 0 and kz = n/2 planes
+// (visited through its Re element) sets its conjugate partner.
+template <typename T>
+__global__ void k_part_mirror(cx<T>* __restrict__ Z, int n, int kp,
+                              const uint32_t* __restrict__ idx, long long cnt) {
+  const int K = n / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long e = idx[i];
+    if (e & 1) continue;
+    const long long f = e >> 1;
+    const int kz = static_cast<int>(f % K);
+    if (kz != 0 && kz != n / 2) continue;
+    const long long r = f / K;
+    const int ky = static_cast<int>(r % n), kx = static_cast<int>(r / n);
+    const int cx_ = (n - kx) & (n - 1), cy = (n - ky) & (n - 1);
+    const cx<T> v = Z[r * kp + kz];
+    Z[((long long)cx_ * n + cy) * kp + kz] = mkc<T>(v.x, -v.y);
   }
 }
 

@@ -129,6 +129,27 @@ def test_c3_rank_order_permutation_bit_exact(prec):
     assert np.array_equal(fidx[canon], ref_idx)
     assert np.array_equal(fbins[canon], ref_bins)
     # within each bin, the GPU's order is the stable descending order of its keys
+    _check_bin_orders(fidx, fkeys, fbins)
+    # the real/imaginary-part reading of the Fourier-space matching on the
+    # same projected field: 2 elements per matched mode, same check
+    s = torch.tensor(_STATE["s0"], dtype=ctx.dtype, device=DEV)
+    ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0)
+    info = ctx.project_rankmatch(s, _lib.IC_ROM_FOURIER_REIM, event=20)
+    assert info["n_fourier"] == ref_idx.size
+    fidx, fkeys, fbins = ctx.rom_order(1)
+    assert fidx.size == 2 * ref_idx.size
+    canon = np.argsort(fidx, kind="stable")
+    elem = np.empty(2 * ref_idx.size, dtype=np.int64)
+    elem[0::2], elem[1::2] = 2 * ref_idx, 2 * ref_idx + 1
+    assert np.array_equal(fidx[canon], elem)
+    assert np.array_equal(fbins[canon], np.repeat(ref_bins, 2))
+    _check_bin_orders(fidx, fkeys, fbins)
+
+
+def _check_bin_orders(fidx, fkeys, fbins):
+    """The dumped order, bin by bin, is the oracle's stable descending order
+    of the dumped keys in canonical index order."""
+    canon = np.argsort(fidx, kind="stable")
     bins_c = fbins[canon]
     keys_c = fkeys[canon].astype(np.float64)
     start = 0

@@ -81,6 +81,53 @@ def test_rom_fourier_permutation_and_values(prec):
     assert rel_l2(after, ref) <= (2e-3 if prec == "f32" else 1e-10)
 
 
+def reim_elements(ref_idx, ref_bins):
+    """Element indices 2 f + c of the Re/Im reading and their bins, in
+    canonical (ascending element) order."""
+    e = np.empty(2 * ref_idx.size, dtype=np.int64)
+    e[0::2], e[1::2] = 2 * ref_idx, 2 * ref_idx + 1
+    return e, np.repeat(ref_bins, 2)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rom_fourier_reim_permutation_and_values(prec):
+    """Real/imaginary-part reading of the Fourier-space matching: the GPU's
+    matched elements and bins are the oracle's, its order within every bin is
+    the oracle's stable descending sort of its own keys (bit-exact), its keys
+    are the parts of its own transform, and the matched field agrees with the
+    oracle's."""
+    require_gpu()
+    cfg, mdl, ctx, R, N, s0 = prepared(prec)
+    n, L = cfg["n_part"], cfg["box"]
+    s = to_dev(s0, prec)
+    before = to_np(s)
+    info = ctx.project_rankmatch(s, _lib.IC_ROM_FOURIER_REIM, event=3)
+    after = to_np(s)
+    idx, keys, bins = ctx.rom_order(1)
+    ref_idx, ref_bins, _ = rom.fourier_mode_sets(n, L)
+    elem, ebins = reim_elements(ref_idx, ref_bins)
+    assert info["n_fourier"] == ref_idx.size
+    assert idx.size == elem.size
+    canon = np.argsort(idx, kind="stable")
+    assert np.array_equal(idx[canon], elem)
+    assert np.array_equal(bins[canon], ebins)
+    for b in np.unique(bins):
+        m = bins == b
+        gi, gk = idx[m], keys[m].astype(np.float64)
+        c = np.argsort(gi, kind="stable")
+        expect = gi[c][rom.descending_order(gk[c])]
+        assert np.array_equal(gi, expect), b
+    z = fourier.rfft3(before).reshape(-1) / n ** 1.5
+    parts = np.where(idx % 2 == 0, z[idx // 2].real, z[idx // 2].imag)
+    assert np.max(np.abs(keys - parts)) <= (2e-6 if prec == "f32" else 1e-13)
+    ref, _ = rom.rom_fourier_reim(before, L, cfg["seed"], 3)
+    err = rel_l2(after, ref)
+    print("Re/Im matching %s: rel L2 against the oracle %.3e" % (prec, err))
+    assert err <= (2e-3 if prec == "f32" else 1e-10)
+    with pytest.raises(_lib.IcError):
+        ctx.project_rankmatch(s, _lib.IC_ROM_FOURIER | _lib.IC_ROM_FOURIER_REIM, event=4)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_lbfgs_trajectory_matches_oracle(prec):
     """20 projected L-BFGS iterations on c1 with rank-order matching every 5.
