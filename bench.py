@@ -13,10 +13,15 @@ Also reported: the same loop with the FP64 instantiation of the kernels; a
 per-kernel HIP-event table from a profiling pass run before the timed region;
 the roofline of the dominant kernel (largest share of that table), whose
 launches are timed with HIP events on the library stream during the timed
-region itself (algorithmic bytes per launch / average launch time, against
-the 8 TB/s HBM peak), with its measured HBM traffic when a hardware-counter
-summary taken on the current sources is present under profiles/; the FP64 CPU
-oracle's rate estimated from a bounded sample on the host cores; and one
+region itself: algorithmic bytes per launch from the byte ledger of one
+gradient evaluation (each field a kernel must read or write counted once, in
+units of U = one particle-grid field and U_m = one mesh field) divided by the
+average launch time, against the 8 TB/s HBM peak, with the implementation's
+own per-launch byte count beside it and its measured HBM traffic when a
+hardware-counter summary taken on the current sources is present under
+profiles/; the whole evaluation against the same ledger (1167 U at 10 steps)
+for FP32 and FP64; the FP64 CPU oracle timed on the host cores on whole
+loss + gradient evaluations of the same problem at 32^3 and 128^3; and one
 timing of a 256^3 FP32 real FFT round trip through torch.fft (hipFFT/rocFFT)
 beside the same round trip through this library's passes, for comparison
 only.
@@ -96,6 +101,31 @@ def run_steps(ctx, s, g, L, first, k, rom_every):
     return L, evals, roms
 
 
+# Algorithmic bytes per launch from the evaluation's byte ledger: (a, b)
+# means a U + b U_m, U = one particle-grid field (N_p^3 elements) and
+# U_m = one mesh field (N_m^3), each field a kernel must read or write
+# counted once (accumulation as a read and a write).
+LEDGER = {
+    "cic_paint_vec": (6, 6),   # positions, cotangent in; 3 meshes accumulated
+    "force_adjoint": (15, 4),  # positions, p_bar in/out, d_bar in/out; 3 force meshes, rho_bar
+    "pm_step": (12, 3),        # positions, momenta in/out; 3 force meshes
+    "cic_paint": (3, 2),       # positions in; density accumulated
+    "data_adjoint": (13, 0),   # positions, momenta, seed in; d_bar, p_bar out
+    "loss": (5, 0),            # density, counts, response, s in; seed out
+    "fft_r2c_z": (0, 2),       # real field in, half spectrum out (mesh chains)
+    "fft_y": (0, 2),
+    "fft_c2r_z": (0, 2),
+}
+
+
+def ledger_eval_units(n_steps):
+    """Ledger of one loss + gradient evaluation in U (N_m = N_p): forward
+    89 (whitening, 2LPT) + 25 (first force) + 37 per step + 14 (last kick,
+    RSD, data paint) + 5 (loss); adjoint 13 (data paint and RSD) + 51 per
+    force VJP (n_steps + 1 of them) + 90 (2LPT, whitening, prior)."""
+    return 89 + 25 + 37 * n_steps + 14 + 5 + 13 + 51 * (n_steps + 1) + 90
+
+
 def kernel_rows(ctx):
     """Kernel rows of the timing report (tile-window statistics dropped)."""
     return [r for r in ctx.timing_report() if not r["name"].startswith("tiles_")]
@@ -147,24 +177,68 @@ def stored_traffic(kernel, dtype_tag):
     return float(m.group(1)), os.path.relpath(path, ROOT)
 
 
-def roofline(table, live, dtype_tag):
+def ledger_bytes(name, cfg, elem):
+    """Ledger bytes of one launch of a kernel, or None when the ledger has
+    no row of its own for it (the x passes count (1 + m) half spectra, as the
+    library's own figure does)."""
+    if name not in LEDGER:
+        return None
+    a, b = LEDGER[name]
+    return float(elem) * (a * cfg["n_part"] ** 3 + b * cfg["n_mesh"] ** 3)
+
+
+def roofline(table, live, dtype_tag, cfg):
     """Dominant kernel (largest total time in the profiling pass) and its
-    algorithmic bandwidth from the launches timed live in the timed region."""
+    algorithmic bandwidth from the launches timed live in the timed region,
+    on the ledger's bytes."""
     tot = sum(r["ms"] for r in table)
     avg_ms = live["ms"] / live["count"]
-    gbs = live["bytes"] / (avg_ms * 1e-3) / 1e9
-    kernels = {r["name"]: dict(launches=r["count"], total_ms=round(r["ms"], 3),
-                               avg_us=round(1e3 * r["ms"] / r["count"], 2),
-                               gbs=round(r["bytes"] / (r["ms"] / r["count"] * 1e-3) / 1e9, 1)
-                               if r["bytes"] > 0 else None,
-                               share=round(r["ms"] / tot, 4)) for r in table}
+    kernels = {}
+    for r in table:
+        avg = r["ms"] / r["count"]
+        lb = ledger_bytes(r["name"], cfg, 4)
+        kernels[r["name"]] = dict(
+            launches=r["count"], total_ms=round(r["ms"], 3), avg_us=round(1e3 * avg, 2),
+            gbs_impl=round(r["bytes"] / (avg * 1e-3) / 1e9, 1) if r["bytes"] > 0 else None,
+            gbs_ledger=round(lb / (avg * 1e-3) / 1e9, 1) if lb else None,
+            share=round(r["ms"] / tot, 4))
+    lb = ledger_bytes(live["name"], cfg, 4)
+    if lb is None:
+        lb = live["bytes"]
+    gbs = lb / (avg_ms * 1e-3) / 1e9
     traffic, source = stored_traffic(live["name"], dtype_tag)
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic),
                 kernel=live["name"], launches_timed=live["count"],
-                avg_us=round(1e3 * avg_ms, 2), bytes_per_launch=live["bytes"],
+                avg_us=round(1e3 * avg_ms, 2), bytes_per_launch=lb,
+                bytes_per_launch_impl=live["bytes"],
+                ledger="%s U + %s U_m, U = 4 N_p^3 bytes, U_m = 4 N_m^3 bytes"
+                % LEDGER.get(live["name"], ("?", "?")),
                 traffic_source=source), kernels
+
+
+def eval_roofline(ctx, s, cfg, elem, n=10):
+    """Whole loss + gradient evaluations at s (3 untimed, then n timed by the
+    wall clock with the device synchronised around them) against the
+    ledger of one evaluation (N_m = N_p only)."""
+    import torch
+    for _ in range(3):
+        ctx.loss_and_grad(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ctx.loss_and_grad(s)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / n
+    out = dict(ms_per_eval=round(ms, 3), evals=n)
+    if cfg["n_mesh"] == cfg["n_part"]:
+        units = ledger_eval_units(cfg["n_steps"])
+        b = float(elem) * units * cfg["n_part"] ** 3
+        out.update(ledger_units=units, ledger_gb=round(b / 1e9, 2),
+                   achieved_gbs=round(b / (ms * 1e-3) / 1e9, 1),
+                   frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    return out
 
 
 def fft_compare(ctx):
@@ -195,59 +269,46 @@ def fft_compare(ctx):
 
 
 def cpu_baseline(cfg):
-    """FP64 oracle rate at this workload, estimated from a bounded sample.
+    """The FP64 oracle on the host cores: one whole loss + gradient
+    evaluation each of the same problem at 32^3 particles (box scaled to keep
+    the cell size) and at 128^3, with mock counts from the oracle's own
+    forward model.  The oracle's cost grows linearly with the particle count
+    (its CIC passes dominate), so the benchmark's rate is the 128^3 rate
+    divided by the particle-count ratio; both measured times are reported."""
 
-    The oracle's evaluation cost is dominated by its CIC passes, whose cost is
-    linear in the particle count.  Sample: one CIC paint and one CIC readout
-    of the oracle on this workload's particle set; scale: the ratio of a full
-    oracle loss + gradient evaluation to that same paint + readout pair,
-    measured on the same configuration at 64^3 particles."""
-    import numpy as np
-
-    from oracle import cic
+    from oracle import fourier
     from oracle.model import Model, Problem
     from paper_2604_26823_amd import inputs
 
-    def model_for(c):
-        fields = {k: c[k] for k in Problem.__dataclass_fields__ if k in c}
-        return Model(Problem(**fields))
-
-    def pair_time(mdl, d):
-        x = mdl.q + d
+    def timed_eval(n):
+        c = dict(cfg, n_part=n, n_mesh=n * cfg["n_mesh"] // cfg["n_part"],
+                 box=cfg["box"] * n / cfg["n_part"])
+        R = inputs.response_field(c)  # same cell size and galaxies per cell as cfg
+        mdl = Model(Problem(**{k: c[k] for k in Problem.__dataclass_fields__ if k in c}))
+        sd = inputs.seeds(cfg["id"])
+        s_true = inputs.white_noise(n, sd["truth"])
+        N = inputs.poisson_counts(mdl.observe(mdl.forward(s_true), R), R, c["r_min"],
+                                  sd["counts"])
+        s0 = inputs.white_noise(n, sd["start"])
         t0 = time.perf_counter()
-        rho = cic.paint(x, mdl.p.n_mesh, mdl.dm)
-        cic.readout(x, rho, mdl.dm)
+        mdl.loss_and_grad(s0, N, R)
         return time.perf_counter() - t0
 
-    small = dict(cfg, n_part=64, n_mesh=64 * cfg["n_mesh"] // cfg["n_part"],
-                 box=cfg["box"] * 64 / cfg["n_part"])
-    R = inputs.response_field(small)
-    small["nbar"] = inputs.nbar_for(small, R)
-    ms = model_for(small)
-    s = inputs.white_noise(64, 7)
-    N = inputs.poisson_counts(ms.observe(ms.forward(s), R), R, small["r_min"], 8)
-    t0 = time.perf_counter()
-    ms.loss_and_grad(s, N, R)
-    t_eval_small = time.perf_counter() - t0
-    d_small, _, _ = ms.lpt(s)
-    ratio = t_eval_small / pair_time(ms, d_small * 10)
-
-    big = model_for(cfg)
-    rng = np.random.default_rng(1)
-    d = rng.normal(0.0, 2.0 * cfg["box"] / cfg["n_part"], (3, cfg["n_part"] ** 3))
-    t_pair = pair_time(big, d)
-    t_eval = ratio * t_pair
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    return dict(value=round(1.0 / t_eval, 6), unit="grad evals/s", cores=min(cores, 16),
+    t_small = timed_eval(32)
+    n_mid = min(128, cfg["n_part"])
+    t_mid = timed_eval(n_mid)
+    ratio = (cfg["n_part"] / n_mid) ** 3
+    t_eval = t_mid * ratio
+    lin = t_mid / t_small / (n_mid / 32) ** 3
+    return dict(value=round(1.0 / t_eval, 6), unit="grad evals/s", cores=fourier._workers(),
                 kind="oracle",
-                sample="oracle CIC paint + readout of the %d^3 particle set (%.1f s) x "
-                       "ratio %.1f of a full oracle loss+gradient to that pair measured at "
-                       "64^3 on the same configuration; estimated %.0f s per evaluation"
-                       % (cfg["n_part"], t_pair, ratio, t_eval),
-                seconds_per_eval=round(t_eval, 1))
+                sample="whole oracle loss+gradient evaluations of this problem in this run: "
+                       "%.2f s at 32^3, %.1f s at %d^3 (cost per particle %.2fx the 32^3 one); "
+                       "rate at %d^3 = 1 / (%d^3 time x %.0f particle-count ratio) = 1 / %.0f s"
+                       % (t_small, t_mid, n_mid, lin, cfg["n_part"], n_mid, ratio, t_eval),
+                seconds_32=round(t_small, 3), seconds_mid=round(t_mid, 2), n_mid=n_mid,
+                seconds_per_eval_scaled=round(t_eval, 1),
+                threads_note="scipy.fft workers = cores; CIC passes single-threaded")
 
 
 def main():
@@ -286,7 +347,9 @@ def main():
         % (a.warmup, a.profile_steps, a.steps))
     r32 = timed_loop(ctx, s, a.steps, a.warmup, rom_every, max(1, a.profile_steps))
     log("bench: FP32 %d evals in %.3f s" % (r32["evals"], r32["seconds"]))
-    roof, table = roofline(r32["table"], r32["live"], "fp32")
+    roof, table = roofline(r32["table"], r32["live"], "fp32", cfg)
+    log("bench: FP32 whole-evaluation timing")
+    ev32 = eval_roofline(ctx, s, cfg, 4)
     fftc = None
     if not a.no_fft_compare:
         log("bench: FFT round-trip comparison")
@@ -296,19 +359,20 @@ def main():
     r32.pop("g")
     torch.cuda.empty_cache()
 
-    r64 = None
+    r64 = ev64 = None
     if not a.no_fp64:
         log("bench: FP64 context")
         ctx64, s64, _, _ = setup(cfg, "f64", counts, s_start)
         r64 = timed_loop(ctx64, s64, a.steps, a.warmup, rom_every)
         r64.pop("g")
+        ev64 = eval_roofline(ctx64, s64, cfg, 8)
         log("bench: FP64 %d evals in %.3f s" % (r64["evals"], r64["seconds"]))
         del ctx64, s64
         torch.cuda.empty_cache()
 
     cpu = None
     if not a.no_cpu_baseline:
-        log("bench: CPU oracle sample")
+        log("bench: CPU oracle evaluations")
         cpu = cpu_baseline(cfg)
 
     value = r32["evals"] / r32["seconds"]
@@ -335,6 +399,7 @@ def main():
             "value": round(r64["evals"] / r64["seconds"], 3), "unit": "grad evals/s",
             "evaluations": r64["evals"], "ms_per_step": round(1e3 * r64["seconds"] / a.steps, 3)},
         "roofline": roof,
+        "eval_roofline": {"fp32": ev32, "fp64": ev64},
         "kernels": table,
         "fft_compare": fftc,
         "workspace_gb": round(ws_gb, 2),

@@ -42,7 +42,9 @@ int ic_op_multiplier(ic_ctx* ctx, int kind_bits, int axis_a, int axis_b,
 int ic_op_paint(ic_ctx* ctx, int grid, const void* disp, void* rho);
 
 /* Particle-mesh force F_n = sum_c W(x_n - c) g(c), g = -grad lap^-1 delta_m,
- * at x = q + disp; force is [3][n_part^3]. */
+ * at x = q + disp; force is [3][n_part^3].  The paint, force chain and
+ * readout are the forward model's own kernels (the readout is the step
+ * kernel's, with a unit kick from zero momentum and no drift). */
 int ic_op_force(ic_ctx* ctx, const void* disp, void* force);
 
 /* 2LPT displacement d0 and momentum p0 at a_init from white noise s
@@ -82,14 +84,12 @@ int ic_host_coefficients(const ic_problem* p, double* out, size_t n);
 
 /* Per-kernel timing with HIP events on the context stream: enable != 0
  * starts recording (resetting the totals), 0 stops.  ic_timing_report
- * writes "name count total_ms bytes_per_launch" lines into buf, where
- * bytes_per_launch counts each field a launch reads or writes once; while
- * every kernel is recorded it also appends the tile-window statistics
- * ("tiles_<kernel> windows 0 cells", "tiles_direct_<kernel> tiles 0 0",
- * "tiles_max_<kernel> cells 0 0").  ic_timing_only starts recording the
- * launches of one kernel name only (kernel: a name the report uses, not
- * NULL), with no window statistics, so timed code is otherwise unchanged;
- * ic_timing(ctx, 0) stops it. */
+ * writes "name count total_ms bytes_per_launch" lines into buf (IC_ERR_
+ * INVALID_ARG when len is too small), where bytes_per_launch is the
+ * implementation's own count: each buffer a launch reads or writes, once.
+ * ic_timing_only starts recording the launches of one kernel name only
+ * (kernel: a name the report uses, not NULL), so timed code is otherwise
+ * unchanged; ic_timing(ctx, 0) stops it. */
 int ic_timing(ic_ctx* ctx, int enable);
 int ic_timing_only(ic_ctx* ctx, const char* kernel);
 int ic_timing_report(ic_ctx* ctx, char* buf, size_t len);

@@ -8,9 +8,13 @@
 // atomics, an exclusive scan, a scatter of the state into block order), and
 // every paint and readout then runs over work items of at most 1024 particles
 // of one block, with the block's window in LDS:
-//   * paints accumulate in FP64 LDS windows (ds_add_f64; the FP32 LDS atomic
-//     add of gfx950 runs at a small fraction of the FP64 rate) and flush each
-//     non-zero window cell with one global atomic;
+//   * paints accumulate in FP64 LDS windows (ds_add_f64); a block's only
+//     item stores its 8^3 own cells (the items of a block with several add
+//     them atomically), its z halo into a one-value-per-eight-cells field
+//     the consumer adds while reading, and its x/y halo into a staging
+//     slot that a second pass adds along whole grid rows: global float
+//     atomics are served past the XCD's L2 and were the paints' largest
+//     cost;
 //   * gathers read their mesh fields from a window loaded with coalesced
 //     loads.
 // Unlike windows around Lagrangian patches, these windows cannot overflow,
@@ -414,6 +418,8 @@ struct Item {
   unsigned b;
   int o[3];
   unsigned s0, s1;
+  unsigned i;       // item index
+  bool single;      // the block's only item (it holds at most kChunk particles)
 };
 
 template <bool CONTIG>
@@ -432,6 +438,8 @@ __device__ __forceinline__ bool item_of(const Items& it, const Layout& L, Item& 
   m.s0 = v.y;
   const unsigned e = it.start[v.x + 1];
   m.s1 = (m.s0 + kChunk < e) ? m.s0 + kChunk : e;
+  m.i = i;
+  m.single = e - it.start[v.x] <= static_cast<unsigned>(kChunk);
   block_origin(m.b, L, m.o);
   return true;
 }
@@ -484,28 +492,135 @@ __device__ __forceinline__ void zero_window(double* acc, int nf) {
   for (int k = threadIdx.x; k < nf * kWin; k += kThreads) acc[k] = 0.0;
 }
 
-// Adds the non-zero cells of nf FP64 windows into the mesh fields dst.p[f].
+// The window's halo, its 217 cells with a coordinate 8, belongs to the
+// blocks above.  The 64 cells above in z only (kx, ky < 8, kz = 8) land on
+// the lowest z layer of the block above in z; the 153 with kx = 8 or ky = 8
+// are numbered x face (81), then y face without it (72).
+constexpr int kHaloXY = kW * kW + kB * kW;
+
+__device__ __forceinline__ int halo_xy_index(int kx, int ky, int kz) {
+  return kx == kB ? ky * kW + kz : kW * kW + kx * kW + kz;
+}
+
+// Flush of nf FP64 windows; the fields and zh are zero before the paint.
+// * The block's own 8^3 cells: plain stores when this item is the block's
+//   only one (no other item of the launch writes them), else global atomic
+//   adds of the non-zero cells.
+// * The z halo: into zh, one value per lowest-z-layer cell of every block
+//   (zh[f][((x << lm) | y) << lnb | bz], a grid field of one value per eight
+//   cells along z), stored or atomically added by the same rule; the
+//   consumer adds it to the cell (x, y, 8 bz).
+// * The x and y halos: into this item's slot of the halo staging
+//   (nf x kHaloXY values), added into the cells by k_halo_rows.
+// Single-item blocks thus flush without global atomics.
 template <typename T>
-__device__ __forceinline__ void flush_window(const int o[3], const Layout& L, const double* acc,
-                                             int nf, const MPtrs<T>& dst) {
+__device__ __forceinline__ void flush_owned(const Item& m, const Layout& L, const double* acc,
+                                            int nf, const MPtrs<T>& dst, T* __restrict__ zh,
+                                            T* __restrict__ halo) {
   constexpr int kIt = (kWin + kThreads - 1) / kThreads;
+  T* hs = halo + static_cast<size_t>(m.i) * nf * kHaloXY;
+  const long long zplane = 1ll << (2 * L.lm + L.lnb);  // zh values per field (n^3 / 8)
+  const unsigned bmask = (1u << L.lnb) - 1;
 #pragma unroll
   for (int j = 0; j < kIt; ++j) {
     const int k = static_cast<int>(threadIdx.x) + j * kThreads;
     if (k >= kWin) continue;
-    const unsigned c = win_cell(o, k, L);
-    for (int f = 0; f < nf; ++f) {
-      const T v = static_cast<T>(acc[f * kWin + k]);
-      if (v != T(0)) pk::atomic_add(dst.p[f] + c, v);
+    const int kx = k / (kW * kW), r = k - kx * kW * kW;
+    const int ky = r / kW, kz = r - ky * kW;
+    if (kx < kB && ky < kB) {
+      T* out[4];
+      long long c;
+      if (kz < kB) {
+        c = win_cell(m.o, k, L);
+        for (int f = 0; f < nf; ++f) out[f] = dst.p[f];
+      } else {
+        const unsigned bz = ((static_cast<unsigned>(m.o[2]) >> kLB) + 1) & bmask;
+        c = ((static_cast<long long>(m.o[0] + kx) << L.lm | (m.o[1] + ky)) << L.lnb) | bz;
+        for (int f = 0; f < nf; ++f) out[f] = zh + f * zplane;
+      }
+      for (int f = 0; f < nf; ++f) {
+        const T v = static_cast<T>(acc[f * kWin + k]);
+        if (m.single)
+          out[f][c] = v;
+        else if (v != T(0))
+          pk::atomic_add(out[f] + c, v);
+      }
+    } else {
+      const int h = halo_xy_index(kx, ky, kz);
+      for (int f = 0; f < nf; ++f) hs[f * kHaloXY + h] = static_cast<T>(acc[f * kWin + k]);
     }
   }
+}
+
+// Number of grid rows (x, y) with x or y on a block's lowest layer, and the
+// coordinates of row r: first the planes x = 8 i (all y), then the rows
+// y = 8 i of the other x.
+__host__ __device__ __forceinline__ long long face_rows(const Layout& L) {
+  const long long n = 1ll << L.lm, nb = 1ll << L.lnb;
+  return nb * n + (n - nb) * nb;
+}
+
+__device__ __forceinline__ void face_row(long long r, const Layout& L, int& x, int& y) {
+  const long long n = 1ll << L.lm, nb = 1ll << L.lnb;
+  if (r < nb * n) {
+    x = static_cast<int>(r >> L.lm) << kLB;
+    y = static_cast<int>(r & (n - 1));
+  } else {
+    const long long q = r - nb * n;
+    const int xi = static_cast<int>(q >> L.lnb);  // index among x not divisible by 8
+    x = (xi / (kB - 1)) * kB + xi % (kB - 1) + 1;
+    y = static_cast<int>(q & (nb - 1)) << kLB;
+  }
+}
+
+// After a paint of one order: every cell of the face rows gets the x and y
+// halo values that the items of the blocks below it in x or y (with or
+// without z) wrote for it.  One thread per cell of those rows, z fastest;
+// istart: the order's item starts per block (nb + 1).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ halo, int nf,
+                                                        const unsigned* __restrict__ istart,
+                                                        Layout L, MPtrs<T> dst) {
+  const long long t = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (t >= face_rows(L) << L.lm) return;
+  int cx, cy;
+  face_row(t >> L.lm, L, cx, cy);
+  const int cz = static_cast<int>(t & ((1ll << L.lm) - 1));
+  const int l[3] = {cx & (kB - 1), cy & (kB - 1), cz & (kB - 1)};
+  const unsigned bm = (1u << L.lnb) - 1;
+  const unsigned bb[3] = {static_cast<unsigned>(cx >> kLB), static_cast<unsigned>(cy >> kLB),
+                          static_cast<unsigned>(cz >> kLB)};
+  T sum[4] = {T(0), T(0), T(0), T(0)};
+  for (int a = 2; a < 8; ++a) {  // a = (ax ay az) as bits 2 1 0, ax or ay set
+    const int ax = (a >> 2) & 1, ay = (a >> 1) & 1, az = a & 1;
+    if ((ax && l[0]) || (ay && l[1]) || (az && l[2])) continue;
+    const unsigned nbk = (((bb[0] - ax) & bm) << (2 * L.lnb)) | (((bb[1] - ay) & bm) << L.lnb) |
+                         ((bb[2] - az) & bm);
+    const int h = halo_xy_index(ax ? kB : l[0], ay ? kB : l[1], az ? kB : l[2]);
+    for (unsigned i = istart[nbk]; i < istart[nbk + 1]; ++i) {
+      const T* hs = halo + static_cast<size_t>(i) * nf * kHaloXY + h;
+      for (int f = 0; f < nf; ++f) sum[f] += hs[f * kHaloXY];
+    }
+  }
+  const long long c = ((static_cast<long long>(cx) << L.lm | cy) << L.lm) | cz;
+  for (int f = 0; f < nf; ++f) dst.p[f][c] += sum[f];
+}
+
+// cell (x, y, 8 bz) += zh[(x, y, bz)] for one field of the grid (the
+// consumers that read a paint's field directly).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_add_zh(T* __restrict__ rho, const T* __restrict__ zh,
+                                                     long long nz) {
+  const long long i = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (i < nz) rho[i << kLB] += zh[i];
 }
 
 // rho(c) += sum_n W(q_n + d_n - c) over the items of one order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, long long P,
                                                       int lp, Grid<T> g, Layout L, Items it,
-                                                      T* __restrict__ rho) {
+                                                      T* __restrict__ rho, T* __restrict__ zh,
+                                                      T* __restrict__ halo) {
   __shared__ double acc[kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
@@ -529,12 +644,11 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
     });
   }
   __syncthreads();
-  flush_window<T>(m.o, L, acc, 1, MPtrs<T>{{rho}});
+  flush_owned<T>(m, L, acc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart; v
-// of slot a is read at slot src[a] (the order the cotangents were left in)
-// and written to v_out[a], in this order, for the force adjoint.
+// of slot a is read at slot src[a] (the order the cotangents were left in).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ d,
                                                           const T* __restrict__ v, T coef,
@@ -542,7 +656,8 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
                                                           Layout L, Items it, T* __restrict__ out,
                                                           long long M,
                                                           const unsigned* __restrict__ src,
-                                                          T* __restrict__ v_out) {
+                                                          T* __restrict__ zh,
+                                                          T* __restrict__ halo) {
   __shared__ double acc[3 * kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
@@ -556,8 +671,6 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     if (!ok[k]) continue;
     pk::load3(d, P, a, dsp[k]);
     pk::load3(v, P, static_cast<long long>(src[a]), vv[k]);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) v_out[q * P + a] = vv[k][q];
   }
   zero_window(acc, 3);
   __syncthreads();
@@ -577,7 +690,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     });
   }
   __syncthreads();
-  flush_window<T>(m.o, L, acc, 3, MPtrs<T>{{out, out + M, out + 2 * M}});
+  flush_owned<T>(m, L, acc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
 }
 
 // Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
@@ -653,18 +766,19 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
   }
 }
 
-// Position cotangent of one force evaluation (see pk::k_force_adjoint) with
-// g (three meshes) and rho_bar read from one four-field window.  p_bar is
-// already in this order (written by the cotangent paint) and is updated in
-// place; d_bar of slot a is read at slot src[a] of the order it was left in
-// (the next order, or the data order) and the update goes to dbar_out[a], so
-// the move between orders costs no pass of its own.
+// Position cotangent of one force evaluation with cotangent v = coef p_bar:
+// d_bar += sum_c grad W(x - c) [sum_j v_j g_j(c) + rho_bar(c)], then the
+// drift adjoint p_bar += drift d_bar; g (three meshes) and rho_bar are read
+// from one four-field window.  p_bar and d_bar of slot a are read at slot
+// src[a] of the order they were left in (the next order, or the data order)
+// and the updates go to pbar_out[a] and dbar_out[a] in this order, so the
+// move between orders costs no pass of its own.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
-    const T* __restrict__ d, T* __restrict__ pbar, const T* __restrict__ dbar, T coef,
+    const T* __restrict__ d, const T* __restrict__ pbar, const T* __restrict__ dbar, T coef,
     const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
     int lp, Grid<T> gm, Layout L, Items it, const unsigned* __restrict__ src,
-    T* __restrict__ dbar_out) {
+    T* __restrict__ dbar_out, T* __restrict__ pbar_out) {
   __shared__ T lds[4 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
@@ -677,8 +791,9 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
     ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
     if (!ok[k]) continue;
     pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(pbar, P, a[k], pb[k]);
-    pk::load3(dbar, P, static_cast<long long>(src[a[k]]), db[k]);
+    const long long sa = static_cast<long long>(src[a[k]]);
+    pk::load3(pbar, P, sa, pb[k]);
+    pk::load3(dbar, P, sa, db[k]);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M, rho_bar}}, 4, lds);
   __syncthreads();
@@ -699,7 +814,7 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
     for (int q = 0; q < 3; ++q) {
       db[k][q] += xb[q] * gm.inv_cell;
       dbar_out[q * P + a[k]] = db[k][q];
-      if (drift != T(0)) pbar[q * P + a[k]] = pb[k][q] + drift * db[k][q];
+      pbar_out[q * P + a[k]] = pb[k][q] + drift * db[k][q];
     }
   }
 }
@@ -785,7 +900,9 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
                                                            const T* __restrict__ p, long long P,
                                                            int lp, pk::Rsd<T> rsd, Grid<T> gd,
                                                            Layout Ld, Items it,
-                                                           T* __restrict__ rho) {
+                                                           T* __restrict__ rho,
+                                                           T* __restrict__ zh,
+                                                           T* __restrict__ halo) {
   __shared__ double acc[kWin];
   Item m;
   if (!item_of<false>(it, Ld, m)) return;
@@ -813,7 +930,7 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
     });
   }
   __syncthreads();
-  flush_window<T>(m.o, Ld, acc, 1, MPtrs<T>{{rho}});
+  flush_owned<T>(m, Ld, acc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // Adjoint of the RSD + data paint (see pk::k_data_adjoint) over the data

@@ -140,6 +140,14 @@ class Engine final : public EngineBase {
     bkey_ = c.take<uint32_t>(P_);
     brank_ = c.take<uint32_t>(P_);
     bsums_ = c.take<uint2>(1024);
+    // halos of the paints (blocks.h): the x/y staging, one slot of
+    // nf x kHaloXY values per work item (three fields on the mesh orders, one
+    // on the data order); the z halos, one value per eight cells of each
+    // painted field (three mesh fields; the data grid's apart, since the
+    // loss reads it after the adjoint's paints began)
+    hstage_ = c.take<T>((size_t)std::max<long long>(3ll * mim_, mid_) * bk::kHaloXY);
+    zh_ = c.take<T>(3 * M_ / kZHalo);
+    zhd_ = c.take<T>(P_ / kZHalo);
     tmpd_ = c.take<T>(3 * P_);
     tmpp_ = c.take<T>(3 * P_);
     dsd_ = c.take<T>(3 * P_);
@@ -361,12 +369,23 @@ class Engine final : public EngineBase {
     paint_lattice(static_cast<const T*>(disp), grid, static_cast<T*>(rho));
   }
 
+  // The readout runs in the hot path's step kernel on the block order the
+  // paint sorted the particles into: a kick of one from zero momentum with
+  // no drift leaves the force itself as the new momentum, which goes back
+  // to the lattice order.
   void op_force(const void* disp, void* force) override {
     const T* d = static_cast<const T*>(disp);
-    paint_lattice(d, 1, rhom_);
-    force_from_density(gtape_);
-    pk::k_readout<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-        d, gtape_, M_, static_cast<T*>(force), P_, lp_, gmesh());
+    paint_lattice(d, 1, rhom_, false);  // positions of order 0 in tmpd_, ids in dids_
+    force_from_density(gtape_);         // adds the z halo left in zh_
+    fill(tmpp_, T(0), 3 * P_);
+    bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+        tmpd_, tmpp_, gtape_, M_, T(1), T(0), P_, lp_, gmesh(), Lm_,
+        items(mesh_order(0), dids_), dbar2_, pbar2_, nullptr, nullptr, nullptr);
+    IC_LAUNCHED();
+    T* F = static_cast<T*>(force);
+    bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+        dids_, bk::Ptrs<T>{{pbar2_, pbar2_ + P_, pbar2_ + 2 * P_}},
+        bk::MPtrs<T>{{F, F + P_, F + 2 * P_}}, 3, P_);
     IC_LAUNCHED();
   }
 
@@ -609,18 +628,45 @@ class Engine final : public EngineBase {
     IC_LAUNCHED();
   }
 
-  // rho += CIC density of the state in order o (positions d, ids id).
+  // Second pass of a paint of order o: the x/y halo staging added along the
+  // grid rows through the blocks' lowest x or y layers, for nf fields.
+  void halo_rows(const Order& o, const bk::Layout& L, int nf, const bk::MPtrs<T>& dst) {
+    const long long cells = bk::face_rows(L) << L.lm;
+    auto sc = timer_.scope("halo_rows", (double)o.max_items * nf * bk::kHaloXY * sizeT() +
+                                            2.0 * nf * cells * sizeT());
+    bk::k_halo_rows<T><<<grid_for(cells, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
+        hstage_, nf, o.istart, L, dst);
+    IC_LAUNCHED();
+  }
+
+  // rho = CIC density of the state in order o (positions d, ids id), its
+  // z halo left in zh (ncells / 8 values) for the consumer; rho and zh are
+  // zeroed here.
   void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
-             const bk::Layout& L, T* rho, long long ncells) {
-    auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
-    bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L, items(o, id),
-                                                             rho);
+             const bk::Layout& L, T* rho, T* zh, long long ncells) {
+    fill(rho, T(0), ncells);
+    fill(zh, T(0), ncells / kZHalo);
+    {
+      auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
+      bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L,
+                                                                  items(o, id), rho, zh, hstage_);
+      IC_LAUNCHED();
+    }
+    halo_rows(o, L, 1, bk::MPtrs<T>{{rho}});
+  }
+
+  // cell (x, y, 8 k) of rho += zh[(x, y, k)]: a paint's z halo into the
+  // field, for the callers that read the field itself.
+  void add_zh(T* rho, const T* zh, long long ncells) {
+    const long long nz = ncells / kZHalo;
+    bk::k_add_zh<T><<<grid_for(nz, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(rho, zh, nz);
     IC_LAUNCHED();
   }
 
   // rho = CIC density of displacements d given in lattice order (sorted into
-  // the scratch order o first; tmpd_ receives the sorted positions).
-  void paint_lattice(const T* d, int grid, T* rho) {
+  // the scratch order o first; tmpd_ receives the sorted positions); with
+  // complete = false the z halo stays in zh_ for a consumer that adds it.
+  void paint_lattice(const T* d, int grid, T* rho, bool complete = true) {
     const pk::Grid<T> g = grid ? gmesh() : gdata();
     const bk::Layout& L = grid ? Lm_ : Ld_;
     const Order o = grid ? mesh_order(0) : data_order();
@@ -629,8 +675,8 @@ class Engine final : public EngineBase {
     build_order(o);
     scatter(o, bk::Ptrs<T>{{d, d + P_, d + 2 * P_}},
             bk::MPtrs<T>{{tmpd_, tmpd_ + P_, tmpd_ + 2 * P_}}, 3, nullptr, dids_, dest(-1));
-    fill(rho, T(0), ncells);
-    paint(tmpd_, o, dids_, g, L, rho, ncells);
+    paint(tmpd_, o, dids_, g, L, rho, zh_, ncells);
+    if (complete) add_zh(rho, zh_, ncells);
   }
 
   // ------------------------------------------------------ k-space chains
@@ -644,9 +690,10 @@ class Engine final : public EngineBase {
     return s;
   }
 
-  // outs[j] = Op_{spec_j}[alpha a + beta b] on the chosen grid.
+  // outs[j] = Op_{spec_j}[alpha (a + zh) + beta b] on the chosen grid (zh:
+  // a paint's z halo, nullable).
   void chain_scatter(int grid, const T* a, T alpha, const T* b, T beta, T* const* outs,
-                     const MulSpec* specs, int m) {
+                     const MulSpec* specs, int m, const T* zh = nullptr) {
     auto f = fa(grid);
     const long long H = grid ? Hm_ : Hp_;
     const double U = (double)(grid ? M_ : P_) * sizeT();
@@ -656,7 +703,7 @@ class Engine final : public EngineBase {
     for (int j = 0; j < m; ++j) So[j] = pool_ + (j + 1) * H;
     {
       auto sc = timer_.scope("fft_r2c_z", (b ? 2 : 1) * U + Hb);
-      fft_r2c_z<T>(f, a, alpha, b, beta, S0);
+      fft_r2c_z<T>(f, a, alpha, b, beta, S0, zh);
     }
     {
       auto sc = timer_.scope("fft_y", 2 * Hb);
@@ -681,6 +728,7 @@ class Engine final : public EngineBase {
     T alpha;
     const T* b;
     T beta;
+    const T* zh;  // a paint's z halo added to a (nullable)
   };
 
   // out = sum_j Op_{spec_j}[alpha_j a_j + beta_j b_j] + beta_aux aux.
@@ -695,7 +743,7 @@ class Engine final : public EngineBase {
       cx<T>* Sj = pool_ + j * H;
       {
         auto sc = timer_.scope("fft_r2c_z", (ins[j].b ? 2 : 1) * U + Hb);
-        fft_r2c_z<T>(f, ins[j].a, ins[j].alpha, ins[j].b, ins[j].beta, Sj);
+        fft_r2c_z<T>(f, ins[j].a, ins[j].alpha, ins[j].b, ins[j].beta, Sj, ins[j].zh);
       }
       {
         auto sc = timer_.scope("fft_y", 2 * Hb);
@@ -752,13 +800,12 @@ class Engine final : public EngineBase {
     const double sc = 1.0 / (nbar * (double)M_);
     MulSpec sp[3] = {spec(MUL_GRAD, 0, 0, sc), spec(MUL_GRAD, 1, 0, sc), spec(MUL_GRAD, 2, 0, sc)};
     T* outs[3] = {g, g + M_, g + 2 * M_};
-    chain_scatter(1, rhom_, T(1), nullptr, T(0), outs, sp, 3);
+    chain_scatter(1, rhom_, T(1), nullptr, T(0), outs, sp, 3, zh_);
   }
 
   // Force meshes of the state d_n (order n).
   void force_mesh(int n, T* g) {
-    fill(rhom_, T(0), M_);
-    paint(dslot(n), mesh_order(n), ids(n), gmesh(), Lm_, rhom_, M_);
+    paint(dslot(n), mesh_order(n), ids(n), gmesh(), Lm_, rhom_, zh_, M_);
     force_from_density(g);
   }
 
@@ -833,10 +880,15 @@ class Engine final : public EngineBase {
     scatter(data_order(), state_ptrs(fd, fp), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
             dest(S_));
     fill(rhod_, T(0), P_);
-    auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0));
-    bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(dsd_, psd_, P_, lp_, rsd(), gdata(),
-                                                           Ld_, items(data_order(), dids_), rhod_);
-    IC_LAUNCHED();
+    fill(zhd_, T(0), P_ / kZHalo);
+    {
+      auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0) + 2.0 * P_ * sizeT());
+      bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
+          dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), rhod_, zhd_,
+          hstage_);
+      IC_LAUNCHED();
+    }
+    halo_rows(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}});  // z halo: in zhd_, read by the loss
   }
 
   // Step n: readout of the forces at d_n, kick, drift into (tmpd_, tmpp_) in
@@ -927,7 +979,7 @@ class Engine final : public EngineBase {
       o.k = static_cast<T>(prob_.bias_k);
       fk::k_loss<T><<<g, fk::kRedThreads, 0, st_>>>(
           rhod_, want_loss ? counts_ : nullptr, resp_, s, o, want_loss ? seed_ : nullptr, delta,
-          lambda, part_, P_);
+          lambda, part_, P_, zhd_);
       IC_LAUNCHED();
     }
     if (!t) return;
@@ -976,26 +1028,29 @@ class Engine final : public EngineBase {
       const double r_snap = js >= 0 ? co_.K2[n - 1] / co_.kick[n] : 0.0;
       if (js >= 0) inject(dest(n), js, dbar_, T(1), static_cast<T>(r_snap));
       fill(gbar_, T(0), 3 * M_);
+      fill(zh_, T(0), 3 * M_ / kZHalo);
       {
-        auto sc = timer_.scope("cic_paint_vec", P_ * (9.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
+        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
         bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), pbar2_);
+            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), zh_, hstage_);
         IC_LAUNCHED();
       }
-      GIn ins[3] = {{gbar_, T(1), nullptr, T(0)},
-                    {gbar_ + M_, T(1), nullptr, T(0)},
-                    {gbar_ + 2 * M_, T(1), nullptr, T(0)}};
+      halo_rows(mesh_order(n), Lm_, 3, bk::MPtrs<T>{{gbar_, gbar_ + M_, gbar_ + 2 * M_}});
+      const long long zm = M_ / kZHalo;
+      GIn ins[3] = {{gbar_, T(1), nullptr, T(0), zh_},
+                    {gbar_ + M_, T(1), nullptr, T(0), zh_ + zm},
+                    {gbar_ + 2 * M_, T(1), nullptr, T(0), zh_ + 2 * zm}};
       MulSpec sp[3] = {spec(MUL_GRAD, 0, 0, sc_rho), spec(MUL_GRAD, 1, 0, sc_rho),
                        spec(MUL_GRAD, 2, 0, sc_rho)};
       chain_gather(1, ins, sp, 3, rhobar_, nullptr, T(0));
       const T drift = n >= 1 ? static_cast<T>(co_.Dr[n - 1]) : T(0);
       {
-        // p_bar in order n (pbar2_, from the paint); d_bar read from order
-        // n + 1 (the data order for n = S) through dest(n), written in order n
+        // p_bar and d_bar read from order n + 1 (the data order for n = S)
+        // through dest(n), written in order n
         auto sc = timer_.scope("force_adjoint", P_ * (15.0 * sizeT() + 8.0) + 4.0 * M_ * sizeT());
         bk::k_force_adjoint_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar2_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it,
-            dest(n), dbar2_);
+            dslot(n), pbar_, dbar_, coef, g, rhobar_, M_, drift, P_, lp_, gmesh(), Lm_, it,
+            dest(n), dbar2_, pbar2_);
         IC_LAUNCHED();
       }
       std::swap(dbar_, dbar2_);
@@ -1124,6 +1179,10 @@ class Engine final : public EngineBase {
   uint32_t *idtape_, *desttape_, *ostart_, *oistart_, *dstart_, *distart_, *dids_;
   uint2 *oitems_, *ditems_, *bsums_;
   uint32_t *bcount_, *bkey_, *brank_;
+  T* hstage_ = nullptr;
+  T* zh_ = nullptr;
+  T* zhd_ = nullptr;
+  static_assert(bk::kB == kZHalo, "the z halo spacing is the block side");
   T *tmpd_, *tmpp_, *dsd_, *psd_, *dbar2_, *pbar2_;
   T *vbuf_, *tbuf_;
   uint32_t* dbg_idx_[2];

@@ -29,6 +29,9 @@ struct MulSpec {
 };
 
 constexpr int kMaxMul = 9;
+// Spacing along z of the cells that receive a paint's z halo (the block side
+// of the particle orders).
+constexpr int kZHalo = 8;
 
 struct MulSet {
   int kinds[kMaxMul];
@@ -59,7 +62,8 @@ struct FftArgs {
 
 // out = forward rfft along z of (alpha a + beta b); b may be null.
 template <typename T>
-void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out);
+void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out,
+               const T* zh = nullptr);
 
 // out = alpha * (unnormalised inverse rfft along z of in) + beta * aux (aux may be null).
 template <typename T>

@@ -3,7 +3,7 @@
 
 namespace ic {
 template void fft_r2c_z<float>(const FftArgs<float>&, const float*, float, const float*, float,
-                               cx<float>*);
+                               cx<float>*, const float*);
 template void fft_c2r_z<float>(const FftArgs<float>&, const cx<float>*, float*, float,
                                const float*, float);
 template void fft_y<float>(const FftArgs<float>&, cx<float>*, bool);

@@ -3,7 +3,7 @@
 
 namespace ic {
 template void fft_r2c_z<double>(const FftArgs<double>&, const double*, double, const double*, double,
-                               cx<double>*);
+                               cx<double>*, const double*);
 template void fft_c2r_z<double>(const FftArgs<double>&, const cx<double>*, double*, double,
                                const double*, double);
 template void fft_y<double>(const FftArgs<double>&, cx<double>*, bool);

@@ -162,6 +162,123 @@ __device__ __forceinline__ void fft_line(int lane, cx<T>* buf, LIdx lidx,
   }
 }
 
+// Transforms that keep the last stage in registers.  The last stage of a
+// Stockham plan writes element jb + r n / R_last from butterfly jb, and the
+// first stage (sub-size 1) of a plan that starts with radix R_last reads
+// exactly those elements into butterfly jb.  So a forward transform can end
+// in registers and an inverse transform in the reversed radix order can
+// start from them, with no LDS round trip in between: the fused x passes
+// hold a line's spectrum in registers while it is multiplied (and summed),
+// and need one LDS tile instead of two.
+template <int n>
+struct XPlan {
+  using P = Plan<n>;
+  static constexpr int S = P::S;
+  static constexpr int RL = S == 1 ? P::R0 : (S == 2 ? P::R1 : P::R2);  // last forward radix
+  static constexpr int Q1 = S == 1 ? 1 : (S == 2 ? P::R0 : P::R1);      // inverse radices
+  static constexpr int Q2 = S == 3 ? P::R0 : 1;                         // after RL
+  static constexpr int TPL = P::TPL;
+  static constexpr int NBL = n / RL;
+  static constexpr int BPT = NBL / TPL;
+};
+
+// A stage whose outputs stay in registers: v[b][r] holds element
+// lane + b TPL + r n / R (valid as the last stage, sub-size n / R).
+template <typename T, int n, int R, int TPL, bool FWD, class Load>
+__device__ __forceinline__ void stage_to_regs(int lane, int Ns, const cx<T>* __restrict__ tw,
+                                              Load&& load, cx<T> (&v)[n / R / TPL][R]) {
+  constexpr int NB = n / R;
+  constexpr int BPT = NB / TPL;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int jb = lane + b * TPL;
+    const int k = jb & (Ns - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b][r] = load(jb + r * NB);
+    if (Ns > 1) {
+      const int step = (n / (Ns * R)) * k;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = tw[step * r];
+        if (!FWD) w.y = -w.y;
+        v[b][r] = cmul<T>(v[b][r], w);
+      }
+    }
+    dft<T, R, FWD>(v[b]);
+  }
+}
+
+// A first stage (sub-size 1) from registers: butterfly jb = lane + b TPL
+// takes v[b][r] as its element jb + r n / R and stores element jb R + r.
+// With sync, a barrier precedes the stores (earlier readers of the LDS
+// tile are done).
+template <typename T, int n, int R, int TPL, bool FWD, class Store>
+__device__ __forceinline__ void stage_from_regs(int lane, cx<T> (&v)[n / R / TPL][R],
+                                                Store&& store, bool sync) {
+  constexpr int BPT = n / R / TPL;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) dft<T, R, FWD>(v[b]);
+  if (sync) __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int jb = lane + b * TPL;
+#pragma unroll
+    for (int r = 0; r < R; ++r) store(jb * R + r, v[b][r]);
+  }
+}
+
+// Forward length-n transform from load0 ending in registers (XPlan layout);
+// the first store into buf follows a barrier.
+template <typename T, int n, class Load, class LIdx>
+__device__ __forceinline__ void fft_fwd_to_regs(int lane, cx<T>* buf, LIdx lidx,
+                                                const cx<T>* __restrict__ tw, Load&& load0,
+                                                cx<T> (&v)[XPlan<n>::BPT][XPlan<n>::RL]) {
+  using P = Plan<n>;
+  constexpr int TPL = P::TPL;
+  auto ld = [&](int e) { return buf[lidx(e)]; };
+  auto st = [&](int e, cx<T> x) { buf[lidx(e)] = x; };
+  if constexpr (P::S == 1) {
+    stage_to_regs<T, n, P::R0, TPL, true>(lane, 1, tw, load0, v);
+  } else if constexpr (P::S == 2) {
+    stage<T, n, P::R0, TPL, true>(lane, 1, tw, 1, load0, st, true);
+    __syncthreads();
+    stage_to_regs<T, n, P::R1, TPL, true>(lane, P::R0, tw, ld, v);
+  } else {
+    stage<T, n, P::R0, TPL, true>(lane, 1, tw, 1, load0, st, true);
+    __syncthreads();
+    stage<T, n, P::R1, TPL, true>(lane, P::R0, tw, 1, ld, st, true);
+    __syncthreads();
+    stage_to_regs<T, n, P::R2, TPL, true>(lane, P::R0 * P::R1, tw, ld, v);
+  }
+}
+
+// Inverse length-n transform starting from registers in the XPlan layout,
+// radices in the reversed order, last stage to storeL; the first store into
+// buf follows a barrier.  v is consumed.
+template <typename T, int n, class Store, class LIdx>
+__device__ __forceinline__ void fft_inv_from_regs(int lane, cx<T>* buf, LIdx lidx,
+                                                  const cx<T>* __restrict__ tw,
+                                                  cx<T> (&v)[XPlan<n>::BPT][XPlan<n>::RL],
+                                                  Store&& storeL) {
+  using X = XPlan<n>;
+  constexpr int TPL = X::TPL;
+  auto ld = [&](int e) { return buf[lidx(e)]; };
+  auto st = [&](int e, cx<T> x) { buf[lidx(e)] = x; };
+  if constexpr (X::S == 1) {
+    stage_from_regs<T, n, X::RL, TPL, false>(lane, v, storeL, false);
+  } else if constexpr (X::S == 2) {
+    stage_from_regs<T, n, X::RL, TPL, false>(lane, v, st, true);
+    __syncthreads();
+    stage<T, n, X::Q1, TPL, false>(lane, X::RL, tw, 1, ld, storeL, true);
+  } else {
+    stage_from_regs<T, n, X::RL, TPL, false>(lane, v, st, true);
+    __syncthreads();
+    stage<T, n, X::Q1, TPL, false>(lane, X::RL, tw, 1, ld, st, true);
+    __syncthreads();
+    stage<T, n, X::Q2, TPL, false>(lane, X::RL * X::Q1, tw, 1, ld, storeL, true);
+  }
+}
+
 // ---------------------------------------------------------------- sizing
 template <typename T, int N> struct ZCfg {
   static constexpr int n = N / 2;
@@ -185,7 +302,7 @@ template <typename T, int N> struct SCfg {  // strided C2C passes
   static constexpr int LP = LINES + 1;  // padded LDS element stride
 };
 
-template <typename T, int N> struct FCfg {  // fused x passes (two LDS tiles)
+template <typename T, int N> struct FCfg {  // fused x passes (one LDS tile)
   static constexpr int TPL = Plan<N>::TPL;
   static constexpr int LINES = (N <= 16) ? 64
                                : (sizeof(T) == 4 ? (N <= 512 ? 16 : 8)
@@ -200,10 +317,14 @@ __device__ __forceinline__ void load_table(cx<T>* dst, const cx<T>* __restrict__
 }
 
 // ------------------------------------------------------------ z pass R2C
+// zh (nullable): a paint's z halo, one value per eight cells along z, added
+// to the cells z = 0 mod 8 of a (the flat index of cell g of the input is
+// g, of its z-halo value g / 8).
 template <typename T, int N>
 __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
     const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
-    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines, int kp) {
+    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines, int kp,
+    const T* __restrict__ zh) {
   using C = ZCfg<T, N>;
   constexpr int n = C::n;
   __shared__ cx<T> buf[C::LINES * C::LS];
@@ -218,7 +339,9 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
   const cx<T>* bin = b ? reinterpret_cast<const cx<T>*>(b + (size_t)line * N) : nullptr;
   auto load0 = [&](int e) -> cx<T> {
     if (!valid) return mkc<T>(0, 0);
-    cx<T> v = cscale<T>(ain[e], alpha);
+    cx<T> u = ain[e];
+    if (zh && (e & (kZHalo / 2 - 1)) == 0) u.x += zh[((size_t)line * N + 2 * e) / kZHalo];
+    cx<T> v = cscale<T>(u, alpha);
     if (bin) {
       cx<T> w = bin[e];
       v.x += beta * w.x;
@@ -350,14 +473,15 @@ struct InPtrs {
   const cx<T>* p[kMaxMul];
 };
 
-// Forward x FFT, then m inverse x FFTs of the multiplied spectrum.
+// Forward x FFT, then m inverse x FFTs of the multiplied spectrum; the
+// forward result stays in registers (XPlan layout) across the m inverses.
 template <typename T, int N>
 __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
     const cx<T>* __restrict__ in, OutPtrs<T> outs, MulSet ms, int m,
     const T* __restrict__ wtab, T L_over_2pi, const cx<T>* __restrict__ twg, int nlines,
     int K, int kp) {
   using C = FCfg<T, N>;
-  __shared__ cx<T> A[N * C::LP];
+  using X = XPlan<N>;
   __shared__ cx<T> B[N * C::LP];
   __shared__ cx<T> tw[N];
   load_table<T>(tw, twg, N);
@@ -372,31 +496,37 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
   const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
   auto lidx = [&](int e) { return e * C::LP + l; };
   auto load_in = [&](int e) -> cx<T> { return valid ? in[line + e * stride] : mkc<T>(0, 0); };
-  auto store_A = [&](int e, cx<T> v) { A[lidx(e)] = v; };
-  fft_line<T, N, true>(lane, B, lidx, tw, 1, load_in, store_A);
-  __syncthreads();
+  cx<T> V[X::BPT][X::RL];
+  fft_fwd_to_regs<T, N>(lane, B, lidx, tw, load_in, V);
   for (int j = 0; j < m; ++j) {
+    cx<T> W[X::BPT][X::RL];
+#pragma unroll
+    for (int b = 0; b < X::BPT; ++b) {
+#pragma unroll
+      for (int r = 0; r < X::RL; ++r) {
+        const int e = lane + b * X::TPL + r * X::NBL;
+        const int ix = wave_index(e, N);
+        const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
+        const int n2 = ix * ix + iy * iy + iz * iz;
+        W[b][r] = apply_mult<T>(V[b][r], ms, j, n2, dk, wtab, L_over_2pi);
+      }
+    }
     cx<T>* dst = outs.p[j];
-    auto load_m = [&](int e) -> cx<T> {
-      const int ix = wave_index(e, N);
-      const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
-      const int n2 = ix * ix + iy * iy + iz * iz;
-      return apply_mult<T>(A[lidx(e)], ms, j, n2, dk, wtab, L_over_2pi);
-    };
     auto store_o = [&](int e, cx<T> v) {
       if (valid) dst[line + e * stride] = v;
     };
-    fft_line<T, N, false>(lane, B, lidx, tw, 1, load_m, store_o);
+    fft_inv_from_regs<T, N>(lane, B, lidx, tw, W, store_o);
   }
 }
 
-// Sum over m inputs of multiplier * forward x FFT, then one inverse x FFT.
+// Sum over m inputs of multiplier * forward x FFT (accumulated in
+// registers), then one inverse x FFT.
 template <typename T, int N>
 __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
     InPtrs<T> ins, MulSet ms, int m, cx<T>* out, const T* __restrict__ wtab, T L_over_2pi,
     const cx<T>* __restrict__ twg, int nlines, int K, int kp) {
   using C = FCfg<T, N>;
-  __shared__ cx<T> A[N * C::LP];
+  using X = XPlan<N>;
   __shared__ cx<T> B[N * C::LP];
   __shared__ cx<T> tw[N];
   load_table<T>(tw, twg, N);
@@ -410,29 +540,31 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
   const int iy = wave_index(ky, N), iz = kz;
   const int dy = (ky == N / 2) ? 0 : iy, dz = (kz == N / 2) ? 0 : iz;
   auto lidx = [&](int e) { return e * C::LP + l; };
+  cx<T> acc[X::BPT][X::RL];
   for (int j = 0; j < m; ++j) {
     const cx<T>* src = ins.p[j];
     auto load_in = [&](int e) -> cx<T> {
       return valid ? src[line + e * stride] : mkc<T>(0, 0);
     };
-    auto acc_A = [&](int e, cx<T> v) {
-      const int ix = wave_index(e, N);
-      const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
-      const int n2 = ix * ix + iy * iy + iz * iz;
-      cx<T> t = apply_mult<T>(v, ms, j, n2, dk, wtab, L_over_2pi);
-      if (j == 0)
-        A[lidx(e)] = t;
-      else
-        A[lidx(e)] = cadd<T>(A[lidx(e)], t);
-    };
-    fft_line<T, N, true>(lane, B, lidx, tw, 1, load_in, acc_A);
+    cx<T> V[X::BPT][X::RL];
+    fft_fwd_to_regs<T, N>(lane, B, lidx, tw, load_in, V);
+#pragma unroll
+    for (int b = 0; b < X::BPT; ++b) {
+#pragma unroll
+      for (int r = 0; r < X::RL; ++r) {
+        const int e = lane + b * X::TPL + r * X::NBL;
+        const int ix = wave_index(e, N);
+        const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
+        const int n2 = ix * ix + iy * iy + iz * iz;
+        const cx<T> t = apply_mult<T>(V[b][r], ms, j, n2, dk, wtab, L_over_2pi);
+        acc[b][r] = j == 0 ? t : cadd<T>(acc[b][r], t);
+      }
+    }
   }
-  __syncthreads();
-  auto load_A = [&](int e) { return A[lidx(e)]; };
   auto store_o = [&](int e, cx<T> v) {
     if (valid) out[line + e * stride] = v;
   };
-  fft_line<T, N, false>(lane, B, lidx, tw, 1, load_A, store_o);
+  fft_inv_from_regs<T, N>(lane, B, lidx, tw, acc, store_o);
 }
 
 // ------------------------------------------------- layout conversion
@@ -483,13 +615,14 @@ inline MulSet make_set(const MulSpec* specs, int m) {
 }  // namespace fftk
 
 template <typename T>
-void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out) {
+void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out,
+               const T* zh) {
   fftk::dispatch_n<T>(f.n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     using C = fftk::ZCfg<T, N>;
     const int nlines = f.n * f.n;
     fftk::k_r2c_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        a, alpha, b, beta, out, f.tw, nlines, f.kp);
+        a, alpha, b, beta, out, f.tw, nlines, f.kp, zh);
   });
   IC_LAUNCHED();
 }

@@ -34,13 +34,6 @@ __global__ void k_fill(T* __restrict__ x, T v, long long n) {
     x[i] = v;
 }
 
-template <typename T>
-__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    b[i] = a[i];
-}
-
 // mu2 = phi_xx phi_yy + phi_xx phi_zz + phi_yy phi_zz - phi_xy^2 - phi_xz^2 - phi_yz^2
 // (phi holds xx, yy, zz, xy, xz, yz, P apart).
 template <typename T>
@@ -108,12 +101,15 @@ template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_loss(
     const T* __restrict__ rho, const int* __restrict__ counts, const T* __restrict__ R,
     const T* __restrict__ s, Obs<T> o, T* __restrict__ seed, T* __restrict__ delta_out,
-    T* __restrict__ lambda_out, double* __restrict__ part, long long n) {
+    T* __restrict__ lambda_out, double* __restrict__ part, long long n,
+    const T* __restrict__ zh) {
   __shared__ double sh[kRedThreads / 64];
   double chi = 0, ss = 0, cnt = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    const T delta = rho[i] - T(1);
+    // the data paint's z halo completes the cells z = 0 mod 8
+    const T rh = rho[i] + ((zh && (i & 7) == 0) ? zh[i >> 3] : T(0));
+    const T delta = rh - T(1);
     T sd = T(0);
     if (delta_out) delta_out[i] = delta;
     if (R) {
@@ -123,11 +119,11 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
         // u = 1 + delta is the painted density itself: taken from rho, not
         // from 1 + (rho - 1), whose cancellation would leave nearly empty
         // cells (u near the floor) with FP32 rounding of order 1e-7 / u
-        const T u = rho[i] > T(kUFloor) ? rho[i] : T(kUFloor);
+        const T u = rh > T(kUFloor) ? rh : T(kUFloor);
         const T sig = T(1) / (T(1) + exp(-o.k * (delta - o.delta_th)));
         const T ua = pow(u, o.alpha);
         lam = o.nbar * r * ua * sig;
-        const T du = rho[i] > T(kUFloor) ? o.alpha * ua / u : T(0);
+        const T du = rh > T(kUFloor) ? o.alpha * ua / u : T(0);
         dlam = o.nbar * r * (du * sig + ua * o.k * sig * (T(1) - sig));
       } else {
         lam = o.nbar * r * (T(1) + o.bias * delta);

@@ -1,6 +1,7 @@
-// Particle kernels: cloud-in-cell paint and readout, the fused kick-drift-
-// paint step, redshift-space distortion with the data-grid paint, and their
-// adjoints (gfx950).
+// Particle building blocks shared by the block-ordered kernels (blocks.h)
+// and the lightcone (lightcone.h): cloud-in-cell stencils and weights, the
+// readout of the force meshes, and the redshift-space distortion with its
+// transpose (gfx950).
 //
 // Particles are lattice points q_n = n dq plus a displacement d_n stored in
 // structure-of-arrays form [3][P] in lattice order, so consecutive threads
@@ -133,45 +134,6 @@ __device__ __forceinline__ void load3(const T* __restrict__ v, long long P, long
   out[2] = v[2 * P + n];
 }
 
-// rho(c) += sum_n W(q_n + d_n - c).
-template <typename T>
-__global__ __launch_bounds__(256) void k_paint(const T* __restrict__ d, long long P, int lp,
-                                               Grid<T> g, T* __restrict__ rho) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3];
-    load3(d, P, n, dsp);
-    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
-    for_corners(s, g.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
-  }
-}
-
-// g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), j = 0..2 (three meshes
-// M apart).
-template <typename T>
-__global__ __launch_bounds__(256) void k_paint_vec(const T* __restrict__ d,
-                                                   const T* __restrict__ v, T coef, long long P,
-                                                   int lp, Grid<T> g, T* __restrict__ out,
-                                                   long long M) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], vv[3];
-    load3(d, P, n, dsp);
-    load3(v, P, n, vv);
-    Stencil<T> s = stencil(idx, g.ratio, dsp, g.inv_cell, g.cell);
-    const T v0 = coef * vv[0], v1 = coef * vv[1], v2 = coef * vv[2];
-    for_corners(s, g.lm, [&](long long c, T w, T, T, T) {
-      atomic_add(out + c, w * v0);
-      atomic_add(out + M + c, w * v1);
-      atomic_add(out + 2 * M + c, w * v2);
-    });
-  }
-}
-
 // Readout of the three force meshes at particle positions: F_j = sum W g_j.
 template <typename T>
 __device__ __forceinline__ void readout3(const Stencil<T>& s, int lm, const T* __restrict__ g,
@@ -182,40 +144,6 @@ __device__ __forceinline__ void readout3(const Stencil<T>& s, int lm, const T* _
     F[1] += w * g[M + c];
     F[2] += w * g[2 * M + c];
   });
-}
-
-// Fused step: readout of g at d_cur, kick p += kick F; if dout: drift
-// d_next = d_cur + drift p and paint rho at d_next.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pm_step(const T* __restrict__ dcur, T* __restrict__ p,
-                                                 const T* __restrict__ g, long long M, T kick,
-                                                 T drift, T* __restrict__ dnext,
-                                                 T* __restrict__ rho, long long P, int lp,
-                                                 Grid<T> gr) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], mom[3], F[3];
-    load3(dcur, P, n, dsp);
-    load3(p, P, n, mom);
-    Stencil<T> s = stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
-    readout3(s, gr.lm, g, M, F);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mom[a] += kick * F[a];
-      p[a * P + n] = mom[a];
-    }
-    if (dnext) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        dsp[a] += drift * mom[a];
-        dnext[a * P + n] = dsp[a];
-      }
-      Stencil<T> s2 = stencil(idx, gr.ratio, dsp, gr.inv_cell, gr.cell);
-      for_corners(s2, gr.lm, [&](long long c, T w, T, T, T) { atomic_add(rho + c, w); });
-    }
-  }
 }
 
 // Redshift-space displacement.  mode 1: shift c p_z along z; mode 2: shift
@@ -306,122 +234,6 @@ __device__ __forceinline__ void rsd_transpose(const Rsd<T>& rsd, const int idx[3
       db[a] += cr * (ux * perp_p + up * perp_x);
       pb[a] = rsd.c * ux * u[a];
     }
-  }
-}
-
-// Last kick (readout of g at d), then RSD and the data-grid paint.
-template <typename T>
-__global__ __launch_bounds__(256) void k_final(const T* __restrict__ d, T* __restrict__ p,
-                                               const T* __restrict__ g, long long M, T kick,
-                                               Grid<T> gm, Rsd<T> rsd, Grid<T> gd,
-                                               T* __restrict__ rho_d, long long P, int lp) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], mom[3], F[3], ds[3];
-    load3(d, P, n, dsp);
-    load3(p, P, n, mom);
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
-    readout3(s, gm.lm, g, M, F);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mom[a] += kick * F[a];
-      p[a * P + n] = mom[a];
-    }
-    rsd_shift(rsd, idx, dsp, mom, ds);
-    Stencil<T> s2 = stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
-    for_corners(s2, gd.lm, [&](long long c, T w, T, T, T) { atomic_add(rho_d + c, w); });
-  }
-}
-
-// Adjoint of the RSD + data paint: x_bar_s = sum_c rho_bar(c) grad W(x_s - c),
-// then the transpose of the RSD map; writes d_bar and p_bar.
-template <typename T>
-__global__ __launch_bounds__(256) void k_data_adjoint(const T* __restrict__ d,
-                                                      const T* __restrict__ p, Rsd<T> rsd,
-                                                      Grid<T> gd, const T* __restrict__ rho_bar,
-                                                      T* __restrict__ dbar, T* __restrict__ pbar,
-                                                      long long P, int lp) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], mom[3], ds[3];
-    load3(d, P, n, dsp);
-    load3(p, P, n, mom);
-    rsd_shift(rsd, idx, dsp, mom, ds);
-    Stencil<T> s = stencil(idx, gd.ratio, ds, gd.inv_cell, gd.cell);
-    T xb[3] = {0, 0, 0};
-    for_corners(s, gd.lm, [&](long long c, T, T d0, T d1, T d2) {
-      const T r = rho_bar[c];
-      xb[0] += d0 * r;
-      xb[1] += d1 * r;
-      xb[2] += d2 * r;
-    });
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xb[a] *= gd.inv_cell;
-    T db[3] = {xb[0], xb[1], xb[2]}, pb[3] = {0, 0, 0};
-    rsd_transpose(rsd, idx, dsp, mom, xb, db, pb);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      dbar[a * P + n] = db[a];
-      pbar[a * P + n] = pb[a];
-    }
-  }
-}
-
-// Position cotangent of one force evaluation with cotangent v = coef p_bar:
-// d_bar += sum_c grad W(x - c) [sum_j v_j g_j(c) + rho_bar(c)]; then, when
-// drift != 0, the drift adjoint p_bar += drift d_bar.
-template <typename T>
-__global__ __launch_bounds__(256) void k_force_adjoint(
-    const T* __restrict__ d, T* __restrict__ pbar, T* __restrict__ dbar, T coef,
-    const T* __restrict__ g, const T* __restrict__ rho_bar, long long M, T drift, long long P,
-    int lp, Grid<T> gm) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], pb[3], db[3];
-    load3(d, P, n, dsp);
-    load3(pbar, P, n, pb);
-    load3(dbar, P, n, db);
-    const T v0 = coef * pb[0], v1 = coef * pb[1], v2 = coef * pb[2];
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
-    T xb[3] = {0, 0, 0};
-    for_corners(s, gm.lm, [&](long long c, T, T d0, T d1, T d2) {
-      const T h = v0 * g[c] + v1 * g[M + c] + v2 * g[2 * M + c] + rho_bar[c];
-      xb[0] += d0 * h;
-      xb[1] += d1 * h;
-      xb[2] += d2 * h;
-    });
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      db[a] += xb[a] * gm.inv_cell;
-      dbar[a * P + n] = db[a];
-      if (drift != T(0)) pbar[a * P + n] = pb[a] + drift * db[a];
-    }
-  }
-}
-
-// Position cotangent of the plain readout F = sum W m: x_bar = v . grad (used
-// by the single-stage readout check).
-template <typename T>
-__global__ __launch_bounds__(256) void k_readout(const T* __restrict__ d, const T* __restrict__ g,
-                                                 long long M, T* __restrict__ F, long long P,
-                                                 int lp, Grid<T> gm) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < P;
-       n += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    lattice(n, lp, idx);
-    T dsp[3], f[3];
-    load3(d, P, n, dsp);
-    Stencil<T> s = stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
-    readout3(s, gm.lm, g, M, f);
-    F[n] = f[0];
-    F[P + n] = f[1];
-    F[2 * P + n] = f[2];
   }
 }
 

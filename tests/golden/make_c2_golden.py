@@ -13,7 +13,9 @@ scale of the paper's first (4 Mpc/h) reconstruction level (section 3):
   iteration made;
 * c2_trajectory_perturbed_<eps>.txt (part "trajectory --perturb eps"): the
   same run from the start field times (1 + eps xi), xi white noise of seed 1
-  - how far a rounding-level difference in the input carries along the path.
+  - how far a rounding-level difference in the input carries along the path;
+* c2_counts.npz (part "counts"): the mock galaxy counts all parts use, so
+  that a test can set the same observation without the oracle's forward.
 
 Truth and counts come from the oracle's own forward model (seeds of the
 configuration: truth 2001, counts 2002, start 2003, generator key 2004).
@@ -24,6 +26,7 @@ three hours on 8 cores):
     python tests/golden/make_c2_golden.py trajectory
     python tests/golden/make_c2_golden.py trajectory --perturb 1e-14
     python tests/golden/make_c2_golden.py trajectory --perturb 1e-7
+    python tests/golden/make_c2_golden.py counts
 Calls only the oracle and the seeded input generators."""
 import argparse
 import os
@@ -119,12 +122,19 @@ def part_trajectory(perturb):
             print("iteration %d loss %.12e (%.0f s)" % (it + 1, L, time.time() - t0), flush=True)
 
 
+def part_counts():
+    _, _, _, N, _ = problem()
+    np.savez_compressed(os.path.join(HERE, "c2_counts.npz"), counts=N)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("part", choices=["eval", "trajectory"])
+    ap.add_argument("part", choices=["eval", "trajectory", "counts"])
     ap.add_argument("--perturb", type=float, default=0.0)
     a = ap.parse_args()
     if a.part == "eval":
         part_eval()
+    elif a.part == "counts":
+        part_counts()
     else:
         part_trajectory(a.perturb)
