@@ -507,9 +507,10 @@ __device__ __forceinline__ int halo_xy_index(int kx, int ky, int kz) {
 //   only one (no other item of the launch writes them), else global atomic
 //   adds of the non-zero cells.
 // * The z halo: into zh, one value per lowest-z-layer cell of every block
-//   (zh[f][((x << lm) | y) << lnb | bz], a grid field of one value per eight
-//   cells along z), stored or atomically added by the same rule; the
-//   consumer adds it to the cell (x, y, 8 bz).
+//   (zh[f][(bz << lm | x) << lm | y], a grid field of one value per eight
+//   cells along z, laid out so that a block's 8 x 8 values form runs of 8),
+//   stored or atomically added by the same rule; the consumer adds it to the
+//   cell (x, y, 8 bz).
 // * The x and y halos: into this item's slot of the halo staging
 //   (nf x kHaloXY values), added into the cells by k_halo_rows.
 // Single-item blocks thus flush without global atomics.
@@ -535,7 +536,7 @@ __device__ __forceinline__ void flush_owned(const Item& m, const Layout& L, cons
         for (int f = 0; f < nf; ++f) out[f] = dst.p[f];
       } else {
         const unsigned bz = ((static_cast<unsigned>(m.o[2]) >> kLB) + 1) & bmask;
-        c = ((static_cast<long long>(m.o[0] + kx) << L.lm | (m.o[1] + ky)) << L.lnb) | bz;
+        c = ((static_cast<long long>(bz) << L.lm | (m.o[0] + kx)) << L.lm) | (m.o[1] + ky);
         for (int f = 0; f < nf; ++f) out[f] = zh + f * zplane;
       }
       for (int f = 0; f < nf; ++f) {
@@ -577,8 +578,8 @@ __device__ __forceinline__ void face_row(long long r, const Layout& L, int& x, i
 // halo values that the items of the blocks below it in x or y (with or
 // without z) wrote for it.  One thread per cell of those rows, z fastest;
 // istart: the order's item starts per block (nb + 1).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ halo, int nf,
+template <typename T, int NF>
+__global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ halo,
                                                         const unsigned* __restrict__ istart,
                                                         Layout L, MPtrs<T> dst) {
   const long long t = blockIdx.x * (long long)kThreads + threadIdx.x;
@@ -590,7 +591,9 @@ __global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ ha
   const unsigned bm = (1u << L.lnb) - 1;
   const unsigned bb[3] = {static_cast<unsigned>(cx >> kLB), static_cast<unsigned>(cy >> kLB),
                           static_cast<unsigned>(cz >> kLB)};
-  T sum[4] = {T(0), T(0), T(0), T(0)};
+  T sum[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) sum[f] = T(0);
   for (int a = 2; a < 8; ++a) {  // a = (ax ay az) as bits 2 1 0, ax or ay set
     const int ax = (a >> 2) & 1, ay = (a >> 1) & 1, az = a & 1;
     if ((ax && l[0]) || (ay && l[1]) || (az && l[2])) continue;
@@ -598,21 +601,25 @@ __global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ ha
                          ((bb[2] - az) & bm);
     const int h = halo_xy_index(ax ? kB : l[0], ay ? kB : l[1], az ? kB : l[2]);
     for (unsigned i = istart[nbk]; i < istart[nbk + 1]; ++i) {
-      const T* hs = halo + static_cast<size_t>(i) * nf * kHaloXY + h;
-      for (int f = 0; f < nf; ++f) sum[f] += hs[f * kHaloXY];
+      const T* hs = halo + static_cast<size_t>(i) * NF * kHaloXY + h;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sum[f] += hs[f * kHaloXY];
     }
   }
   const long long c = ((static_cast<long long>(cx) << L.lm | cy) << L.lm) | cz;
-  for (int f = 0; f < nf; ++f) dst.p[f][c] += sum[f];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) dst.p[f][c] += sum[f];
 }
 
-// cell (x, y, 8 bz) += zh[(x, y, bz)] for one field of the grid (the
+// cell (x, y, 8 bz) += zh[(bz, x, y)] for one field of side 2^lm (the
 // consumers that read a paint's field directly).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_add_zh(T* __restrict__ rho, const T* __restrict__ zh,
-                                                     long long nz) {
+                                                     int lm, long long nz) {
   const long long i = blockIdx.x * (long long)kThreads + threadIdx.x;
-  if (i < nz) rho[i << kLB] += zh[i];
+  if (i >= nz) return;
+  const long long xy = i & ((1ll << (2 * lm)) - 1), bz = i >> (2 * lm);
+  rho[(xy << lm) | (bz << kLB)] += zh[i];
 }
 
 // rho(c) += sum_n W(q_n + d_n - c) over the items of one order.

@@ -634,8 +634,11 @@ class Engine final : public EngineBase {
     const long long cells = bk::face_rows(L) << L.lm;
     auto sc = timer_.scope("halo_rows", (double)o.max_items * nf * bk::kHaloXY * sizeT() +
                                             2.0 * nf * cells * sizeT());
-    bk::k_halo_rows<T><<<grid_for(cells, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
-        hstage_, nf, o.istart, L, dst);
+    const unsigned grid = grid_for(cells, bk::kThreads, 1u << 30);
+    if (nf == 3)
+      bk::k_halo_rows<T, 3><<<grid, bk::kThreads, 0, st_>>>(hstage_, o.istart, L, dst);
+    else
+      bk::k_halo_rows<T, 1><<<grid, bk::kThreads, 0, st_>>>(hstage_, o.istart, L, dst);
     IC_LAUNCHED();
   }
 
@@ -657,9 +660,10 @@ class Engine final : public EngineBase {
 
   // cell (x, y, 8 k) of rho += zh[(x, y, k)]: a paint's z halo into the
   // field, for the callers that read the field itself.
-  void add_zh(T* rho, const T* zh, long long ncells) {
+  void add_zh(T* rho, const T* zh, long long ncells, int lg) {
     const long long nz = ncells / kZHalo;
-    bk::k_add_zh<T><<<grid_for(nz, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(rho, zh, nz);
+    bk::k_add_zh<T><<<grid_for(nz, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(rho, zh, lg,
+                                                                                   nz);
     IC_LAUNCHED();
   }
 
@@ -676,7 +680,7 @@ class Engine final : public EngineBase {
     scatter(o, bk::Ptrs<T>{{d, d + P_, d + 2 * P_}},
             bk::MPtrs<T>{{tmpd_, tmpd_ + P_, tmpd_ + 2 * P_}}, 3, nullptr, dids_, dest(-1));
     paint(tmpd_, o, dids_, g, L, rho, zh_, ncells);
-    if (complete) add_zh(rho, zh_, ncells);
+    if (complete) add_zh(rho, zh_, ncells, L.lm);
   }
 
   // ------------------------------------------------------ k-space chains
@@ -979,7 +983,7 @@ class Engine final : public EngineBase {
       o.k = static_cast<T>(prob_.bias_k);
       fk::k_loss<T><<<g, fk::kRedThreads, 0, st_>>>(
           rhod_, want_loss ? counts_ : nullptr, resp_, s, o, want_loss ? seed_ : nullptr, delta,
-          lambda, part_, P_, zhd_);
+          lambda, part_, P_, zhd_, lp_);
       IC_LAUNCHED();
     }
     if (!t) return;

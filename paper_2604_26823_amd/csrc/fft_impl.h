@@ -304,6 +304,9 @@ template <typename T, int N> struct SCfg {  // strided C2C passes
 
 template <typename T, int N> struct FCfg {  // fused x passes (one LDS tile)
   static constexpr int TPL = Plan<N>::TPL;
+  // waves per SIMD the register allocation must allow: the FP32 scatter
+  // otherwise takes just over half the register file (one wave per SIMD)
+  static constexpr int MINW = (sizeof(T) == 4 && N <= 512) ? 2 : 1;
   static constexpr int LINES = (N <= 16) ? 64
                                : (sizeof(T) == 4 ? (N <= 512 ? 16 : 8)
                                                  : (N <= 512 ? 8 : 2));
@@ -318,8 +321,8 @@ __device__ __forceinline__ void load_table(cx<T>* dst, const cx<T>* __restrict__
 
 // ------------------------------------------------------------ z pass R2C
 // zh (nullable): a paint's z halo, one value per eight cells along z, added
-// to the cells z = 0 mod 8 of a (the flat index of cell g of the input is
-// g, of its z-halo value g / 8).
+// to the cells z = 0 mod 8 of a (the value of cell z of line L = x N + y is
+// zh[(z / 8) N^2 + L]).
 template <typename T, int N>
 __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
     const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
@@ -340,7 +343,8 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
   auto load0 = [&](int e) -> cx<T> {
     if (!valid) return mkc<T>(0, 0);
     cx<T> u = ain[e];
-    if (zh && (e & (kZHalo / 2 - 1)) == 0) u.x += zh[((size_t)line * N + 2 * e) / kZHalo];
+    if (zh && (e & (kZHalo / 2 - 1)) == 0)
+      u.x += zh[(size_t)(2 * e / kZHalo) * N * N + line];
     cx<T> v = cscale<T>(u, alpha);
     if (bin) {
       cx<T> w = bin[e];
@@ -476,7 +480,7 @@ struct InPtrs {
 // Forward x FFT, then m inverse x FFTs of the multiplied spectrum; the
 // forward result stays in registers (XPlan layout) across the m inverses.
 template <typename T, int N>
-__global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_scatter(
+__global__ __launch_bounds__((FCfg<T, N>::THREADS), (FCfg<T, N>::MINW)) void k_x_scatter(
     const cx<T>* __restrict__ in, OutPtrs<T> outs, MulSet ms, int m,
     const T* __restrict__ wtab, T L_over_2pi, const cx<T>* __restrict__ twg, int nlines,
     int K, int kp) {

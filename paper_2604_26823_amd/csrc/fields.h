@@ -102,13 +102,16 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
     const T* __restrict__ rho, const int* __restrict__ counts, const T* __restrict__ R,
     const T* __restrict__ s, Obs<T> o, T* __restrict__ seed, T* __restrict__ delta_out,
     T* __restrict__ lambda_out, double* __restrict__ part, long long n,
-    const T* __restrict__ zh) {
+    const T* __restrict__ zh, int lg) {
   __shared__ double sh[kRedThreads / 64];
   double chi = 0, ss = 0, cnt = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
-    // the data paint's z halo completes the cells z = 0 mod 8
-    const T rh = rho[i] + ((zh && (i & 7) == 0) ? zh[i >> 3] : T(0));
+    // the data paint's z halo (layout [z / 8][x][y], grid side 2^lg)
+    // completes the cells z = 0 mod 8
+    const T rh = rho[i] + ((zh && (i & 7) == 0)
+                               ? zh[((i & ((1ll << lg) - 1)) >> 3 << (2 * lg)) | (i >> lg)]
+                               : T(0));
     const T delta = rh - T(1);
     T sd = T(0);
     if (delta_out) delta_out[i] = delta;
