@@ -60,6 +60,25 @@ int ic_op_evolve(ic_ctx* ctx, const void* s, void* d_final, void* p_final);
  * ties keep index order, -0 equals +0. */
 int ic_op_sort_desc(ic_ctx* ctx, const void* values, int64_t n, int32_t* order);
 
+/* Largest n of ic_op_sort_desc_noalloc (2^21 values: a 128^3 field). */
+#define IC_NOALLOC_SORT_MAX (1ll << 21)
+
+/* ic_op_sort_desc without a context, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same stable descending order (order[j] =
+ * index of the j-th largest of the n values; ties keep index order, -0
+ * equals +0), computed by the same kernels, with the sort's keys, indices
+ * and histograms in a file-scope device array of 48 MiB that every device
+ * running the call holds until the process ends.  precision: IC_F32 or
+ * IC_F64 (values: device, of that type); order: device int32[n]; stream: a
+ * hipStream_t (NULL = default stream), synchronised once (the NaN check).
+ * Allocates nothing.  Calls that overlap on one device share the array and
+ * race.  Errors (message in ic_last_error(NULL)): IC_ERR_INVALID_ARG for
+ * n < 0 or n > IC_NOALLOC_SORT_MAX, a null buffer or a bad precision;
+ * IC_ERR_NONFINITE when a value is NaN (order untouched). */
+int ic_op_sort_desc_noalloc(int precision, const void* values, int64_t n, int32_t* order,
+                            void* stream);
+
 /* n draws of the counter-based generator (Philox4x64-10, key = seed,
  * counter (j, sub, stream, event) for j = 0..n-1): kind 0 = N(0,1) normals,
  * 1 = Rayleigh with unit mean square.  out: device, context precision. */

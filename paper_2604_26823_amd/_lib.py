@@ -25,7 +25,7 @@ EXPORTS = [
     "ic_last_error", "ic_set_stream", "ic_set_observation", "ic_forward", "ic_loss_and_grad",
     "ic_vjp", "ic_project_rankmatch", "ic_lbfgs_step", "ic_lbfgs_reset", "ic_upsample_noise",
     "ic_op_rfft", "ic_op_irfft", "ic_op_multiplier", "ic_op_paint", "ic_op_force", "ic_op_lpt",
-    "ic_op_evolve", "ic_op_sort_desc", "ic_op_philox", "ic_debug_rom_order", "ic_timing",
+    "ic_op_evolve", "ic_op_sort_desc", "ic_op_sort_desc_noalloc", "ic_op_philox", "ic_debug_rom_order", "ic_timing",
     "ic_timing_only", "ic_timing_report", "ic_host_coefficients",
 ]
 
@@ -98,6 +98,7 @@ _SIGS = {
     "ic_op_lpt": (_I, [_P, _P, _P, _P]),
     "ic_op_evolve": (_I, [_P, _P, _P, _P]),
     "ic_op_sort_desc": (_I, [_P, _P, ctypes.c_int64, _P]),
+    "ic_op_sort_desc_noalloc": (_I, [_I, _P, ctypes.c_int64, _P, _P]),
     "ic_op_philox": (_I, [_P, _I, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                           ctypes.c_int64, _P]),
     "ic_debug_rom_order": (_I, [_P, _I, _P, _P, _P, ctypes.c_int64,

@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libic_mi355x.so")
 
-SOURCES = ["fft_f32.hip", "fft_f64.hip", "engine_f32.hip", "engine_f64.hip", "cosmo.cpp",
-           "capi.cpp"]
+SOURCES = ["fft_f32.hip", "fft_f64.hip", "engine_f32.hip", "engine_f64.hip", "noalloc.hip",
+           "cosmo.cpp", "capi.cpp"]
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable"]

@@ -52,6 +52,9 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 namespace ic {
 
+void noalloc_sort_desc(int precision, const void* values, int64_t n, int32_t* order,
+                       hipStream_t st);  // noalloc.hip
+
 void validate_problem(const ic_problem& p) {
   auto bad = [](int code, const char* m) { throw ApiError(code, m); };
   if (!pow2(p.n_part) || p.n_part < 8 || p.n_part > 512)
@@ -358,6 +361,20 @@ int ic_timing_report(ic_ctx* ctx, char* buf, size_t len) {
     if (r.size() + 1 > len) throw ic::ApiError(IC_ERR_INVALID_ARG, "report buffer too small");
     std::memcpy(buf, r.c_str(), r.size() + 1);
   });
+}
+
+int ic_op_sort_desc_noalloc(int precision, const void* values, int64_t n, int32_t* order,
+                            void* stream) {
+  try {
+    ic::noalloc_sort_desc(precision, values, n, order, static_cast<hipStream_t>(stream));
+    return IC_OK;
+  } catch (const ic::ApiError& e) {
+    return fail(nullptr, e.code, e.what());
+  } catch (const ic::HipError& e) {
+    return fail(nullptr, IC_ERR_HIP, e.what());
+  } catch (const std::exception& e) {
+    return fail(nullptr, IC_ERR_INVALID_ARG, e.what());
+  }
 }
 
 }  // extern "C"
