@@ -8,7 +8,8 @@
 // atomics, an exclusive scan, a scatter of the state into block order), and
 // every paint and readout then runs over work items of at most 1024 particles
 // of one block, with the block's window in LDS:
-//   * paints accumulate in FP64 LDS windows (ds_add_f64); a block's only
+//   * paints accumulate in LDS windows (FP64 adds for FP64 grids, exact
+//     64-bit fixed-point adds for FP32 grids, see WinAcc); a block's only
 //     item stores its 8^3 own cells (the items of a block with several add
 //     them atomically), its z halo into a one-value-per-eight-cells field
 //     the consumer adds while reading, and its x/y halo into a staging
@@ -488,8 +489,62 @@ __device__ __forceinline__ void load_window(const int o[3], const Layout& L, con
   }
 }
 
-__device__ __forceinline__ void zero_window(double* acc, int nf) {
-  for (int k = threadIdx.x; k < nf * kWin; k += kThreads) acc[k] = 0.0;
+// LDS accumulation of the paint windows.  FP64 grids: FP64 adds
+// (ds_add_f64).  FP32 grids: 64-bit fixed point, value = integer x 2^-e
+// (ds_add_u64 takes about half the time of ds_add_f64 on scattered cells
+// of gfx950, and integer adds are exact, so the window sums do not depend
+// on the order of the atomics).  e is chosen per work item so that nothing
+// overflows: every contribution is at most amax in magnitude (CIC weights
+// are at most 1), a window cell receives at most kChunk of them, and
+// amax 2^e < 2^52, so every partial sum stays below 2^62.  The rounding of
+// a contribution, at most 2^-53 amax, is far below the FP32 result's.
+template <typename T>
+struct WinAcc {
+  using Cell = double;
+  struct Scale {
+    double s, inv;
+  };
+  __device__ static Scale scale_for(double) { return Scale{1.0, 1.0}; }
+  __device__ static void add(Cell* c, double v, const Scale&) { atomicAdd(c, v); }
+  __device__ static double get(Cell c, const Scale&) { return c; }
+};
+template <>
+struct WinAcc<float> {
+  using Cell = unsigned long long;
+  struct Scale {
+    double s, inv;
+  };
+  // 2^e with amax 2^e < 2^52 (amax < 2^k from frexp, e = 52 - k)
+  __device__ static Scale scale_for(double amax) {
+    if (!(amax > 0.0)) return Scale{1.0, 1.0};
+    int k;
+    frexp(amax, &k);
+    return Scale{ldexp(1.0, 52 - k), ldexp(1.0, k - 52)};
+  }
+  __device__ static void add(Cell* c, double v, const Scale& sc) {
+    atomicAdd(c, static_cast<unsigned long long>(__double2ll_rn(v * sc.s)));
+  }
+  __device__ static double get(Cell c, const Scale& sc) {
+    return static_cast<double>(static_cast<long long>(c)) * sc.inv;
+  }
+};
+
+template <typename C>
+__device__ __forceinline__ void zero_window(C* acc, int nf) {
+  for (int k = threadIdx.x; k < nf * kWin; k += kThreads) acc[k] = C(0);
+}
+
+// Largest |x| over the workgroup's threads (red: kThreads / 64 doubles of
+// LDS; every thread gets the result after the barrier the caller places
+// between the two halves).
+__device__ __forceinline__ void wg_max_issue(double x, double* red) {
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+}
+__device__ __forceinline__ double wg_max_finish(const double* red) {
+  double x = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) x = fmax(x, red[w]);
+  return x;
 }
 
 // The window's halo, its 217 cells with a coordinate 8, belongs to the
@@ -515,8 +570,10 @@ __device__ __forceinline__ int halo_xy_index(int kx, int ky, int kz) {
 //   (nf x kHaloXY values), added into the cells by k_halo_rows.
 // Single-item blocks thus flush without global atomics.
 template <typename T>
-__device__ __forceinline__ void flush_owned(const Item& m, const Layout& L, const double* acc,
-                                            int nf, const MPtrs<T>& dst, T* __restrict__ zh,
+__device__ __forceinline__ void flush_owned(const Item& m, const Layout& L,
+                                            const typename WinAcc<T>::Cell* acc,
+                                            const typename WinAcc<T>::Scale& sc, int nf,
+                                            const MPtrs<T>& dst, T* __restrict__ zh,
                                             T* __restrict__ halo) {
   constexpr int kIt = (kWin + kThreads - 1) / kThreads;
   T* hs = halo + static_cast<size_t>(m.i) * nf * kHaloXY;
@@ -540,7 +597,7 @@ __device__ __forceinline__ void flush_owned(const Item& m, const Layout& L, cons
         for (int f = 0; f < nf; ++f) out[f] = zh + f * zplane;
       }
       for (int f = 0; f < nf; ++f) {
-        const T v = static_cast<T>(acc[f * kWin + k]);
+        const T v = static_cast<T>(WinAcc<T>::get(acc[f * kWin + k], sc));
         if (m.single)
           out[f][c] = v;
         else if (v != T(0))
@@ -548,7 +605,7 @@ __device__ __forceinline__ void flush_owned(const Item& m, const Layout& L, cons
       }
     } else {
       const int h = halo_xy_index(kx, ky, kz);
-      for (int f = 0; f < nf; ++f) hs[f * kHaloXY + h] = static_cast<T>(acc[f * kWin + k]);
+      for (int f = 0; f < nf; ++f) hs[f * kHaloXY + h] = static_cast<T>(WinAcc<T>::get(acc[f * kWin + k], sc));
     }
   }
 }
@@ -628,7 +685,8 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
                                                       int lp, Grid<T> g, Layout L, Items it,
                                                       T* __restrict__ rho, T* __restrict__ zh,
                                                       T* __restrict__ halo) {
-  __shared__ double acc[kWin];
+  using A = WinAcc<T>;
+  __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
   bool ok[kPer];
@@ -641,17 +699,18 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
     if (ok[k]) pk::load3(d, P, a, dsp[k]);
   }
   zero_window(acc, 1);
+  const typename A::Scale sc = A::scale_for(1.0);  // weights are at most 1
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (!ok[k]) continue;
     const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], g);
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
-      atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
+      A::add(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w), sc);
     });
   }
   __syncthreads();
-  flush_owned<T>(m, L, acc, 1, MPtrs<T>{{rho}}, zh, halo);
+  flush_owned<T>(m, L, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart; v
@@ -665,7 +724,9 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
                                                           const unsigned* __restrict__ src,
                                                           T* __restrict__ zh,
                                                           T* __restrict__ halo) {
-  __shared__ double acc[3 * kWin];
+  using A = WinAcc<T>;
+  __shared__ typename A::Cell acc[3 * kWin];
+  __shared__ double red[kThreads / 64];
   Item m;
   if (!item_of<false>(it, L, m)) return;
   bool ok[kPer];
@@ -680,7 +741,16 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     pk::load3(v, P, static_cast<long long>(src[a]), vv[k]);
   }
   zero_window(acc, 3);
+  double amax = 0.0;  // largest |coef v| of the item (the weights are at most 1)
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!ok[k]) continue;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) amax = fmax(amax, fabs(static_cast<double>(coef * vv[k][q])));
+  }
+  wg_max_issue(amax, red);
   __syncthreads();
+  const typename A::Scale sc = A::scale_for(wg_max_finish(red));
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (!ok[k]) continue;
@@ -691,13 +761,13 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
       const int c = win_index(m.o, cx, cy, cz);
       const double wd = static_cast<double>(w);
-      atomicAdd(&acc[c], wd * v0);
-      atomicAdd(&acc[kWin + c], wd * v1);
-      atomicAdd(&acc[2 * kWin + c], wd * v2);
+      A::add(&acc[c], wd * v0, sc);
+      A::add(&acc[kWin + c], wd * v1, sc);
+      A::add(&acc[2 * kWin + c], wd * v2, sc);
     });
   }
   __syncthreads();
-  flush_owned<T>(m, L, acc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
+  flush_owned<T>(m, L, acc, sc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
 }
 
 // Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
@@ -910,7 +980,8 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
                                                            T* __restrict__ rho,
                                                            T* __restrict__ zh,
                                                            T* __restrict__ halo) {
-  __shared__ double acc[kWin];
+  using A = WinAcc<T>;
+  __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, Ld, m)) return;
   bool ok[kPer];
@@ -925,6 +996,7 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
     pk::load3(p, P, a, mom[k]);
   }
   zero_window(acc, 1);
+  const typename A::Scale sc = A::scale_for(1.0);  // weights are at most 1
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -933,11 +1005,11 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
     pk::rsd_shift(rsd, idx[k], dsp[k], mom[k], ds);
     const Stencil<T> s = wrapped_stencil(idx[k], ds, gd);
     pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
-      atomicAdd(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w));
+      A::add(&acc[win_index(m.o, cx, cy, cz)], static_cast<double>(w), sc);
     });
   }
   __syncthreads();
-  flush_owned<T>(m, Ld, acc, 1, MPtrs<T>{{rho}}, zh, halo);
+  flush_owned<T>(m, Ld, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // Adjoint of the RSD + data paint (see pk::k_data_adjoint) over the data
