@@ -610,44 +610,39 @@ __device__ __forceinline__ void flush_owned(const Item& m, const Layout& L,
   }
 }
 
-// Number of grid rows (x, y) with x or y on a block's lowest layer, and the
-// coordinates of row r: first the planes x = 8 i (all y), then the rows
-// y = 8 i of the other x.
-__host__ __device__ __forceinline__ long long face_rows(const Layout& L) {
-  const long long n = 1ll << L.lm, nb = 1ll << L.lnb;
-  return nb * n + (n - nb) * nb;
+// Cells that receive x/y halo values: those with x or y on a block's lowest
+// layer (x = 8 i: every y; y = 8 j: x not on such a layer).  They are
+// visited block face by block face, one wavefront per face: 2 nb^3 faces
+// (the x faces of all blocks, then their y faces), 64 cells (lanes) each.
+__host__ __device__ __forceinline__ long long face_waves(const Layout& L) {
+  return 2ll << (3 * L.lnb);
 }
 
-__device__ __forceinline__ void face_row(long long r, const Layout& L, int& x, int& y) {
-  const long long n = 1ll << L.lm, nb = 1ll << L.lnb;
-  if (r < nb * n) {
-    x = static_cast<int>(r >> L.lm) << kLB;
-    y = static_cast<int>(r & (n - 1));
-  } else {
-    const long long q = r - nb * n;
-    const int xi = static_cast<int>(q >> L.lnb);  // index among x not divisible by 8
-    x = (xi / (kB - 1)) * kB + xi % (kB - 1) + 1;
-    y = static_cast<int>(q & (nb - 1)) << kLB;
-  }
-}
-
-// After a paint of one order: every cell of the face rows gets the x and y
-// halo values that the items of the blocks below it in x or y (with or
-// without z) wrote for it.  One thread per cell of those rows, z fastest;
-// istart: the order's item starts per block (nb + 1).
+// After a paint of one order: every face cell gets the x and y halo values
+// that the items of the blocks below it in x or y (with or without z) wrote
+// for it.  A wavefront takes the face of one block: on an x face lane
+// (ly, lz) is cell (8 b0, 8 b1 + ly, 8 b2 + lz), on a y face lane (lx, lz)
+// is cell (8 b0 + lx, 8 b1, 8 b2 + lz) with lx = 0 idle (an x face cell).
+// The main halo value of the face's 64 cells then sits in one contiguous
+// run of the staging of one item, and the four wavefronts of a workgroup
+// take neighbouring faces along z, so the mesh rows they update are
+// 128-byte runs.  istart: the order's item starts per block (nb + 1).
 template <typename T, int NF>
 __global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ halo,
                                                         const unsigned* __restrict__ istart,
                                                         Layout L, MPtrs<T> dst) {
   const long long t = blockIdx.x * (long long)kThreads + threadIdx.x;
-  if (t >= face_rows(L) << L.lm) return;
-  int cx, cy;
-  face_row(t >> L.lm, L, cx, cy);
-  const int cz = static_cast<int>(t & ((1ll << L.lm) - 1));
-  const int l[3] = {cx & (kB - 1), cy & (kB - 1), cz & (kB - 1)};
+  const long long w = t >> 6;
+  if (w >= face_waves(L)) return;
+  const int lane = static_cast<int>(t & 63);
+  const long long nb3 = 1ll << (3 * L.lnb);
+  const bool yface = w >= nb3;
+  const long long q = yface ? w - nb3 : w;
   const unsigned bm = (1u << L.lnb) - 1;
-  const unsigned bb[3] = {static_cast<unsigned>(cx >> kLB), static_cast<unsigned>(cy >> kLB),
-                          static_cast<unsigned>(cz >> kLB)};
+  const unsigned bb[3] = {static_cast<unsigned>(q >> (2 * L.lnb)),
+                          static_cast<unsigned>(q >> L.lnb) & bm, static_cast<unsigned>(q) & bm};
+  const int l[3] = {yface ? lane >> 3 : 0, yface ? 0 : lane >> 3, lane & 7};
+  if (yface && l[0] == 0) return;
   T sum[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) sum[f] = T(0);
@@ -663,7 +658,10 @@ __global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ ha
       for (int f = 0; f < NF; ++f) sum[f] += hs[f * kHaloXY];
     }
   }
-  const long long c = ((static_cast<long long>(cx) << L.lm | cy) << L.lm) | cz;
+  const long long cx = (static_cast<long long>(bb[0]) << kLB) | l[0];
+  const long long cy = (static_cast<long long>(bb[1]) << kLB) | l[1];
+  const long long cz = (static_cast<long long>(bb[2]) << kLB) | l[2];
+  const long long c = (((cx << L.lm) | cy) << L.lm) | cz;
 #pragma unroll
   for (int f = 0; f < NF; ++f) dst.p[f][c] += sum[f];
 }

@@ -383,7 +383,7 @@ class Engine final : public EngineBase {
         items(mesh_order(0), dids_), dbar2_, pbar2_, nullptr, nullptr, nullptr);
     IC_LAUNCHED();
     T* F = static_cast<T*>(force);
-    bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+    bk::k_to_lattice<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
         dids_, bk::Ptrs<T>{{pbar2_, pbar2_ + P_, pbar2_ + 2 * P_}},
         bk::MPtrs<T>{{F, F + P_, F + 2 * P_}}, 3, P_);
     IC_LAUNCHED();
@@ -398,7 +398,7 @@ class Engine final : public EngineBase {
     run_forward(static_cast<const T*>(s));
     T* dd = static_cast<T*>(d);
     T* pp = static_cast<T*>(p);
-    bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+    bk::k_to_lattice<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
         ids(S_), state_ptrs(dslot(S_), pslot(S_)), state_mptrs(dd, pp), 6, P_);
     IC_LAUNCHED();
   }
@@ -614,7 +614,7 @@ class Engine final : public EngineBase {
   void scatter(const Order& o, const bk::Ptrs<T>& src, const bk::MPtrs<T>& dst, int nf,
                const unsigned* ids_src, unsigned* ids_dst, unsigned* dst_slots) {
     auto sc = timer_.scope("sort_scatter", P_ * (2.0 * nf * sizeT() + 20.0));
-    bk::k_scatter<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+    bk::k_scatter<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
         bkey_, brank_, o.start, src, dst, nf, ids_src, ids_dst, dst_slots, P_);
     IC_LAUNCHED();
   }
@@ -623,7 +623,7 @@ class Engine final : public EngineBase {
   void keys_lattice(const T* d, const pk::Grid<T>& g, const bk::Layout& L, unsigned nb) {
     zero_counts(nb);
     auto sc = timer_.scope("sort_keys", P_ * (3.0 * sizeT() + 8.0));
-    bk::k_keys<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+    bk::k_keys<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
         d, nullptr, P_, lp_, g, L, bcount_, bkey_, brank_);
     IC_LAUNCHED();
   }
@@ -631,10 +631,11 @@ class Engine final : public EngineBase {
   // Second pass of a paint of order o: the x/y halo staging added along the
   // grid rows through the blocks' lowest x or y layers, for nf fields.
   void halo_rows(const Order& o, const bk::Layout& L, int nf, const bk::MPtrs<T>& dst) {
-    const long long cells = bk::face_rows(L) << L.lm;
+    const long long waves = bk::face_waves(L);
+    const double cells = (double)(waves / 2) * (64 + 56);
     auto sc = timer_.scope("halo_rows", (double)o.max_items * nf * bk::kHaloXY * sizeT() +
                                             2.0 * nf * cells * sizeT());
-    const unsigned grid = grid_for(cells, bk::kThreads, 1u << 30);
+    const unsigned grid = grid_for(waves * 64, bk::kThreads, 1u << 30);
     if (nf == 3)
       bk::k_halo_rows<T, 3><<<grid, bk::kThreads, 0, st_>>>(hstage_, o.istart, L, dst);
     else
@@ -874,7 +875,7 @@ class Engine final : public EngineBase {
       }
       zero_counts(nbd_);
       auto sc = timer_.scope("sort_keys", P_ * (3.0 * sizeT() + 12.0));
-      bk::k_keys<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+      bk::k_keys<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
           dbar2_, ids(S_), P_, lp_, gdata(), Ld_, bcount_, bkey_, brank_);
       IC_LAUNCHED();
       fd = tmpd_;
@@ -922,7 +923,7 @@ class Engine final : public EngineBase {
       force_mesh(j, gslot(j));
       step(j, false);
       auto sc = timer_.scope("sort_replay", P_ * (12.0 * sizeT() + 4.0));
-      bk::k_to_lattice<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+      bk::k_to_lattice<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
           dest(j), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(j + 1), pslot(j + 1)), 6, P_);
       IC_LAUNCHED();
     }
@@ -960,7 +961,7 @@ class Engine final : public EngineBase {
   void cotangents_back(const unsigned* dest_slots) {
     {
       auto sc = timer_.scope("sort_gather_back", P_ * (12.0 * sizeT() + 4.0));
-      bk::k_gather_back<T><<<grid_for(P_, kThreads, 1u << 30), kThreads, 0, st_>>>(
+      bk::k_gather_back<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
           dest_slots, state_ptrs(dbar_, pbar_), state_mptrs(dbar2_, pbar2_), 6, P_);
       IC_LAUNCHED();
     }

@@ -39,6 +39,20 @@ IC_FFT_PLAN(512, 8, 8, 8)
 IC_FFT_PLAN(1024, 16, 8, 8)
 #undef IC_FFT_PLAN
 
+// Radix plans of the fused x passes, which hold a line's spectrum in
+// registers across several transforms: PlanX for the scatter (one forward,
+// several inverses), PlanG for the gather (several forwards, one inverse);
+// both default to Plan<n>.  The gather at n = 256 takes radix 8 first, so a
+// thread holds 8 values instead of 16 and more waves fit per SIMD.
+template <int n> struct PlanX : Plan<n> {};
+template <int n> struct PlanG : Plan<n> {};
+template <> struct PlanG<256> {
+  static constexpr int R0 = 8, R1 = 8, R2 = 4;
+  static constexpr int S = 3;
+  static constexpr int RMAX = 8;
+  static constexpr int TPL = 256 / RMAX;
+};
+
 // cos and sin of 2 pi m / 16, m = 0..7.
 __device__ constexpr double kC16[8] = {1.0,
                                        0.92387953251128675613,
@@ -170,9 +184,9 @@ __device__ __forceinline__ void fft_line(int lane, cx<T>* buf, LIdx lidx,
 // start from them, with no LDS round trip in between: the fused x passes
 // hold a line's spectrum in registers while it is multiplied (and summed),
 // and need one LDS tile instead of two.
-template <int n>
+template <int n, class PL = PlanX<n>>
 struct XPlan {
-  using P = Plan<n>;
+  using P = PL;
   static constexpr int S = P::S;
   static constexpr int RL = S == 1 ? P::R0 : (S == 2 ? P::R1 : P::R2);  // last forward radix
   static constexpr int Q1 = S == 1 ? 1 : (S == 2 ? P::R0 : P::R1);      // inverse radices
@@ -229,11 +243,11 @@ __device__ __forceinline__ void stage_from_regs(int lane, cx<T> (&v)[n / R / TPL
 
 // Forward length-n transform from load0 ending in registers (XPlan layout);
 // the first store into buf follows a barrier.
-template <typename T, int n, class Load, class LIdx>
+template <typename T, int n, class PL, class Load, class LIdx>
 __device__ __forceinline__ void fft_fwd_to_regs(int lane, cx<T>* buf, LIdx lidx,
                                                 const cx<T>* __restrict__ tw, Load&& load0,
-                                                cx<T> (&v)[XPlan<n>::BPT][XPlan<n>::RL]) {
-  using P = Plan<n>;
+                                                cx<T> (&v)[XPlan<n, PL>::BPT][XPlan<n, PL>::RL]) {
+  using P = PL;
   constexpr int TPL = P::TPL;
   auto ld = [&](int e) { return buf[lidx(e)]; };
   auto st = [&](int e, cx<T> x) { buf[lidx(e)] = x; };
@@ -255,12 +269,12 @@ __device__ __forceinline__ void fft_fwd_to_regs(int lane, cx<T>* buf, LIdx lidx,
 // Inverse length-n transform starting from registers in the XPlan layout,
 // radices in the reversed order, last stage to storeL; the first store into
 // buf follows a barrier.  v is consumed.
-template <typename T, int n, class Store, class LIdx>
+template <typename T, int n, class PL, class Store, class LIdx>
 __device__ __forceinline__ void fft_inv_from_regs(int lane, cx<T>* buf, LIdx lidx,
                                                   const cx<T>* __restrict__ tw,
-                                                  cx<T> (&v)[XPlan<n>::BPT][XPlan<n>::RL],
+                                                  cx<T> (&v)[XPlan<n, PL>::BPT][XPlan<n, PL>::RL],
                                                   Store&& storeL) {
-  using X = XPlan<n>;
+  using X = XPlan<n, PL>;
   constexpr int TPL = X::TPL;
   auto ld = [&](int e) { return buf[lidx(e)]; };
   auto st = [&](int e, cx<T> x) { buf[lidx(e)] = x; };
@@ -302,8 +316,8 @@ template <typename T, int N> struct SCfg {  // strided C2C passes
   static constexpr int LP = LINES + 1;  // padded LDS element stride
 };
 
-template <typename T, int N> struct FCfg {  // fused x passes (one LDS tile)
-  static constexpr int TPL = Plan<N>::TPL;
+template <typename T, int N, class PL = PlanX<N>> struct FCfg {  // fused x passes
+  static constexpr int TPL = PL::TPL;
   // waves per SIMD the register allocation must allow: the FP32 scatter
   // otherwise takes just over half the register file (one wave per SIMD)
   static constexpr int MINW = (sizeof(T) == 4 && N <= 512) ? 2 : 1;
@@ -332,8 +346,7 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
   constexpr int n = C::n;
   __shared__ cx<T> buf[C::LINES * C::LS];
   __shared__ cx<T> tw[N];
-  load_table<T>(tw, twg, N);
-  __syncthreads();
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
   const int lane = threadIdx.x % C::TPL;
   const int l = threadIdx.x / C::TPL;
   const int line = blockIdx.x * C::LINES + l;
@@ -430,8 +443,7 @@ __global__ __launch_bounds__((SCfg<T, N>::THREADS)) void k_strided(
   using C = SCfg<T, N>;
   __shared__ cx<T> buf[N * C::LP];
   __shared__ cx<T> tw[N];
-  load_table<T>(tw, twg, N);
-  __syncthreads();
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
@@ -488,8 +500,7 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS), (FCfg<T, N>::MINW)) void k_x
   using X = XPlan<N>;
   __shared__ cx<T> B[N * C::LP];
   __shared__ cx<T> tw[N];
-  load_table<T>(tw, twg, N);
-  __syncthreads();
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
@@ -501,7 +512,7 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS), (FCfg<T, N>::MINW)) void k_x
   auto lidx = [&](int e) { return e * C::LP + l; };
   auto load_in = [&](int e) -> cx<T> { return valid ? in[line + e * stride] : mkc<T>(0, 0); };
   cx<T> V[X::BPT][X::RL];
-  fft_fwd_to_regs<T, N>(lane, B, lidx, tw, load_in, V);
+  fft_fwd_to_regs<T, N, PlanX<N>>(lane, B, lidx, tw, load_in, V);
   for (int j = 0; j < m; ++j) {
     cx<T> W[X::BPT][X::RL];
 #pragma unroll
@@ -519,22 +530,21 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS), (FCfg<T, N>::MINW)) void k_x
     auto store_o = [&](int e, cx<T> v) {
       if (valid) dst[line + e * stride] = v;
     };
-    fft_inv_from_regs<T, N>(lane, B, lidx, tw, W, store_o);
+    fft_inv_from_regs<T, N, PlanX<N>>(lane, B, lidx, tw, W, store_o);
   }
 }
 
 // Sum over m inputs of multiplier * forward x FFT (accumulated in
 // registers), then one inverse x FFT.
 template <typename T, int N>
-__global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
+__global__ __launch_bounds__((FCfg<T, N, PlanG<N>>::THREADS)) void k_x_gather(
     InPtrs<T> ins, MulSet ms, int m, cx<T>* out, const T* __restrict__ wtab, T L_over_2pi,
     const cx<T>* __restrict__ twg, int nlines, int K, int kp) {
-  using C = FCfg<T, N>;
-  using X = XPlan<N>;
+  using C = FCfg<T, N, PlanG<N>>;
+  using X = XPlan<N, PlanG<N>>;
   __shared__ cx<T> B[N * C::LP];
   __shared__ cx<T> tw[N];
-  load_table<T>(tw, twg, N);
-  __syncthreads();
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
   const int l = threadIdx.x % C::LINES;
   const int lane = threadIdx.x / C::LINES;
   const int line = blockIdx.x * C::LINES + l;
@@ -551,7 +561,7 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
       return valid ? src[line + e * stride] : mkc<T>(0, 0);
     };
     cx<T> V[X::BPT][X::RL];
-    fft_fwd_to_regs<T, N>(lane, B, lidx, tw, load_in, V);
+    fft_fwd_to_regs<T, N, PlanG<N>>(lane, B, lidx, tw, load_in, V);
 #pragma unroll
     for (int b = 0; b < X::BPT; ++b) {
 #pragma unroll
@@ -568,7 +578,7 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS)) void k_x_gather(
   auto store_o = [&](int e, cx<T> v) {
     if (valid) out[line + e * stride] = v;
   };
-  fft_inv_from_regs<T, N>(lane, B, lidx, tw, acc, store_o);
+  fft_inv_from_regs<T, N, PlanG<N>>(lane, B, lidx, tw, acc, store_o);
 }
 
 // ------------------------------------------------- layout conversion
@@ -722,7 +732,7 @@ void fft_x_gather(const FftArgs<T>& f, const cx<T>* const* ins, const MulSpec* s
   const T l2p = static_cast<T>(f.box / (2.0 * 3.14159265358979323846));
   fftk::dispatch_n<T>(f.n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    using C = fftk::FCfg<T, N>;
+    using C = fftk::FCfg<T, N, fftk::PlanG<N>>;
     const int K = N / 2 + 1;
     const int nlines = N * f.kp;
     fftk::k_x_gather<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
