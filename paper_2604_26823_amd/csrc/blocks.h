@@ -610,6 +610,35 @@ __device__ __forceinline__ void flush_owned(const Item& m, const Layout& L,
   }
 }
 
+// Before a paint of one order: zeroes the own cells (nf fields) and the
+// z-halo entries of every block that no single work item owns, i.e. blocks
+// with no particles or with several items (whose items add atomically); a
+// block's only item stores all of them itself.  One wavefront per block:
+// lane (kx, ky) clears the eight cells of its z row and its z-halo entry.
+// istart: the order's item starts per block (nb + 1).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero_unowned(const unsigned* __restrict__ istart,
+                                                           Layout L, int nf, MPtrs<T> dst,
+                                                           T* __restrict__ zh) {
+  const long long t = blockIdx.x * (long long)kThreads + threadIdx.x;
+  const long long b = t >> 6;
+  if (b >= (1ll << (3 * L.lnb))) return;
+  if (istart[b + 1] - istart[b] == 1u) return;
+  const int lane = static_cast<int>(t & 63);
+  int o[3];
+  block_origin(static_cast<unsigned>(b), L, o);
+  const long long cx = o[0] + (lane >> 3), cy = o[1] + (lane & 7);
+  const long long row = ((cx << L.lm) | cy) << L.lm | o[2];
+  const long long zplane = 1ll << (2 * L.lm + L.lnb);
+  const unsigned bz = ((static_cast<unsigned>(o[2]) >> kLB) + 1) & ((1u << L.lnb) - 1);
+  const long long zc = ((static_cast<long long>(bz) << L.lm | cx) << L.lm) | cy;
+  for (int f = 0; f < nf; ++f) {
+#pragma unroll
+    for (int z = 0; z < kB; ++z) dst.p[f][row + z] = T(0);
+    zh[f * zplane + zc] = T(0);
+  }
+}
+
 // Cells that receive x/y halo values: those with x or y on a block's lowest
 // layer (x = 8 i: every y; y = 8 j: x not on such a layer).  They are
 // visited block face by block face, one wavefront per face: 2 nb^3 faces

@@ -628,6 +628,15 @@ class Engine final : public EngineBase {
     IC_LAUNCHED();
   }
 
+  // First pass of a paint of order o into nf fields and their z halo: zero
+  // what no single work item stores (fields and zh need no fill of their own).
+  void zero_unowned(const Order& o, const bk::Layout& L, int nf, const bk::MPtrs<T>& dst, T* zh) {
+    const long long nb = 1ll << (3 * L.lnb);
+    bk::k_zero_unowned<T><<<grid_for(nb * 64, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
+        o.istart, L, nf, dst, zh);
+    IC_LAUNCHED();
+  }
+
   // Second pass of a paint of order o: the x/y halo staging added along the
   // grid rows through the blocks' lowest x or y layers, for nf fields.
   void halo_rows(const Order& o, const bk::Layout& L, int nf, const bk::MPtrs<T>& dst) {
@@ -644,12 +653,11 @@ class Engine final : public EngineBase {
   }
 
   // rho = CIC density of the state in order o (positions d, ids id), its
-  // z halo left in zh (ncells / 8 values) for the consumer; rho and zh are
-  // zeroed here.
+  // z halo left in zh (ncells / 8 values) for the consumer; every cell of
+  // rho and zh is written here.
   void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
              const bk::Layout& L, T* rho, T* zh, long long ncells) {
-    fill(rho, T(0), ncells);
-    fill(zh, T(0), ncells / kZHalo);
+    zero_unowned(o, L, 1, bk::MPtrs<T>{{rho}}, zh);
     {
       auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
       bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L,
@@ -884,8 +892,7 @@ class Engine final : public EngineBase {
     build_order(data_order());
     scatter(data_order(), state_ptrs(fd, fp), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
             dest(S_));
-    fill(rhod_, T(0), P_);
-    fill(zhd_, T(0), P_ / kZHalo);
+    zero_unowned(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}}, zhd_);
     {
       auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0) + 2.0 * P_ * sizeT());
       bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
@@ -1032,8 +1039,7 @@ class Engine final : public EngineBase {
       const int js = n < S_ ? snapshot_index(n) : -1;
       const double r_snap = js >= 0 ? co_.K2[n - 1] / co_.kick[n] : 0.0;
       if (js >= 0) inject(dest(n), js, dbar_, T(1), static_cast<T>(r_snap));
-      fill(gbar_, T(0), 3 * M_);
-      fill(zh_, T(0), 3 * M_ / kZHalo);
+      zero_unowned(mesh_order(n), Lm_, 3, bk::MPtrs<T>{{gbar_, gbar_ + M_, gbar_ + 2 * M_}}, zh_);
       {
         auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
         bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
