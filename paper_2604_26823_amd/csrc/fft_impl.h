@@ -462,9 +462,17 @@ __global__ __launch_bounds__((SCfg<T, N>::THREADS)) void k_strided(
 // version (0 at the Nyquist index).
 __device__ __forceinline__ int wave_index(int i, int N) { return i < N / 2 ? i : i - N; }
 
+// Component a (0, 1, 2) of an integer wave vector; a is the same for the
+// whole workgroup, so this is a select, not an indexed (private memory) load.
+__device__ __forceinline__ int pick(int a, int kx, int ky, int kz) {
+  return a == 0 ? kx : (a == 1 ? ky : kz);
+}
+
+// Multiplier j of ms applied to v at wave vector (kx, ky, kz) in units of the
+// fundamental mode (derivative versions), n2 = |k|^2 in the same units.
 template <typename T>
-__device__ __forceinline__ cx<T> apply_mult(cx<T> v, const MulSet& ms, int j, int n2,
-                                            const int* dk, const T* __restrict__ wtab,
+__device__ __forceinline__ cx<T> apply_mult(cx<T> v, const MulSet& ms, int j, int n2, int kx,
+                                            int ky, int kz, const T* __restrict__ wtab,
                                             T L_over_2pi) {
   const int kinds = ms.kinds[j];
   T f = static_cast<T>(ms.scale[j]);
@@ -472,9 +480,10 @@ __device__ __forceinline__ cx<T> apply_mult(cx<T> v, const MulSet& ms, int j, in
   if (n2 == 0) return mkc<T>(0, 0);
   if (kinds & MUL_WHITE) f *= wtab[n2];
   const T inv = static_cast<T>(1) / static_cast<T>(n2);
-  if (kinds & MUL_HESS) f *= static_cast<T>(dk[ms.ha[j]] * dk[ms.hb[j]]) * inv;
+  if (kinds & MUL_HESS)
+    f *= static_cast<T>(pick(ms.ha[j], kx, ky, kz) * pick(ms.hb[j], kx, ky, kz)) * inv;
   if (kinds & MUL_GRAD) {
-    f *= L_over_2pi * static_cast<T>(dk[ms.ga[j]]) * inv;
+    f *= L_over_2pi * static_cast<T>(pick(ms.ga[j], kx, ky, kz)) * inv;
     return mkc<T>(-v.y * f, v.x * f);  // i f v
   }
   return cscale<T>(v, f);
@@ -521,9 +530,9 @@ __global__ __launch_bounds__((FCfg<T, N>::THREADS), (FCfg<T, N>::MINW)) void k_x
       for (int r = 0; r < X::RL; ++r) {
         const int e = lane + b * X::TPL + r * X::NBL;
         const int ix = wave_index(e, N);
-        const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
         const int n2 = ix * ix + iy * iy + iz * iz;
-        W[b][r] = apply_mult<T>(V[b][r], ms, j, n2, dk, wtab, L_over_2pi);
+        W[b][r] = apply_mult<T>(V[b][r], ms, j, n2, (e == N / 2) ? 0 : ix, dy, dz, wtab,
+                                L_over_2pi);
       }
     }
     cx<T>* dst = outs.p[j];
@@ -568,9 +577,9 @@ __global__ __launch_bounds__((FCfg<T, N, PlanG<N>>::THREADS)) void k_x_gather(
       for (int r = 0; r < X::RL; ++r) {
         const int e = lane + b * X::TPL + r * X::NBL;
         const int ix = wave_index(e, N);
-        const int dk[3] = {(e == N / 2) ? 0 : ix, dy, dz};
         const int n2 = ix * ix + iy * iy + iz * iz;
-        const cx<T> t = apply_mult<T>(V[b][r], ms, j, n2, dk, wtab, L_over_2pi);
+        const cx<T> t = apply_mult<T>(V[b][r], ms, j, n2, (e == N / 2) ? 0 : ix, dy, dz, wtab,
+                                      L_over_2pi);
         acc[b][r] = j == 0 ? t : cadd<T>(acc[b][r], t);
       }
     }
