@@ -102,3 +102,56 @@ def test_c2_density_loss_and_gradient_match_oracle(prec):
     assert ed <= TOL_DENS[prec]
     assert eg <= TOL_GRAD[prec]
     assert el <= TOL_DENS[prec] and ec <= TOL_DENS[prec]
+
+
+def horizon(twin, ref, tol):
+    """Last iteration up to which the oracle's perturbed run stays within
+    tol / 10 of the unperturbed one."""
+    rel = np.abs(twin - ref) / np.abs(ref)
+    bad = np.nonzero(rel > 0.1 * tol)[0]
+    return (bad[0] - 1) if bad.size else len(ref) - 1
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c2_lbfgs_trajectory_matches_oracle(prec):
+    """50 projected L-BFGS iterations (section 2.3.1) with rank-order
+    matching every 20 (section 2.3.2) against the oracle's 50, held to the
+    trajectory bound up to the twin horizon (module docstring), and past it
+    to a final loss within the spread of the oracle's own twins."""
+    require_gpu()
+    cfg, R, counts, s0 = problem()
+    ref, ref_ev = trajectory("c2_trajectory.txt")
+    twin, _ = trajectory("c2_trajectory_perturbed_%s.txt" % TWIN[prec])
+    iters, every = len(ref) - 1, cfg["rom_every"]
+    assert iters == 50 and len(twin) == len(ref)
+    ctx = ctx_for(prec)
+    ctx.lbfgs_reset()
+    s = to_dev(s0, prec)
+    ctx.project_rankmatch(s, _lib.IC_PROJECT, event=0, trial=0)
+    L, g, _ = ctx.loss_and_grad(s)
+    got, ev = [L], [1]
+    for it in range(iters):
+        L, info = ctx.lbfgs_step(s, g, L, it)
+        e = info["evaluations"]
+        if (it + 1) % every == 0:
+            ctx.project_rankmatch(s, _lib.IC_PROJECT | _lib.IC_ROM_REAL | _lib.IC_ROM_FOURIER,
+                                  event=it + 1)
+            ctx.lbfgs_reset()
+            L, _, _ = ctx.loss_and_grad(s, g)
+            e += 1
+        got.append(L)
+        ev.append(e)
+    got = np.array(got)
+    rel = np.abs(got - ref) / np.abs(ref)
+    h = horizon(twin, ref, TOL_TRAJ[prec])
+    spread = float(np.max(np.abs(twin - ref) / np.abs(ref)))
+    print("c2 %s trajectory rel errors: %s" % (prec, " ".join("%.1e" % r for r in rel)))
+    print("c2 %s: oracle twin (perturbed %s) within %.0e up to iteration %d; evaluations GPU %d, "
+          "oracle %d; final loss GPU %.6e, oracle %.6e (rel %.2e); largest twin spread %.2e"
+          % (prec, TWIN[prec], 0.1 * TOL_TRAJ[prec], h, sum(ev), int(ref_ev.sum()), got[-1],
+             ref[-1], rel[-1], spread))
+    assert h >= 3
+    assert np.max(rel[:h + 1]) <= TOL_TRAJ[prec]
+    # past the horizon the runs are different samples of the same descent
+    assert rel[-1] <= max(0.05, 3 * spread)
+    assert got[-1] < got[0]
