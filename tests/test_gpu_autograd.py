@@ -62,7 +62,7 @@ def test_icloss_grad_is_the_oracle_gradient(prec, name):
     L = ICLoss.apply(s, ctx)
     assert L.dim() == 0 and L.dtype == torch.float64
     (gs,) = torch.autograd.grad(L, s)
-    e_L = abs(float(L) - L_ref) / abs(L_ref)
+    e_L = abs(float(L.detach()) - L_ref) / abs(L_ref)
     e_g = rel_l2(to_np(gs), g_ref)
     print("%s %s: loss rel %.3e, autograd gradient rel L2 %.3e" % (name, prec, e_L, e_g))
     assert e_L <= TOL_DENS[prec]
