@@ -373,6 +373,23 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
   dest[a] = s;
 }
 
+// The ids of slot a to slot s = start[key[a]] + rank[a] of the new order,
+// dest[a] = s, and inv[s] = a: the new order's map back to this one, through
+// which the next kernels read the state left in this order.
+static __global__ __launch_bounds__(kThreads) void k_scatter_ids(
+    const unsigned* __restrict__ key, const unsigned* __restrict__ rank,
+    const unsigned* __restrict__ start, const unsigned* __restrict__ ids_src,
+    unsigned* __restrict__ ids_dst, unsigned* __restrict__ dest, unsigned* __restrict__ inv,
+    long long P) {
+  const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (a >= P) return;
+  const unsigned id = ids_src[a];
+  const unsigned s = start[key[a]] + rank[a];
+  ids_dst[s] = id;
+  inv[s] = static_cast<unsigned>(a);
+  dest[a] = s;
+}
+
 // dst_f[a] = src_f[dest[a]] for nf fields: values of the next order brought
 // back to this one.
 template <typename T>
@@ -706,9 +723,14 @@ __global__ __launch_bounds__(kThreads) void k_add_zh(T* __restrict__ rho, const 
   rho[(xy << lm) | (bz << kLB)] += zh[i];
 }
 
-// rho(c) += sum_n W(q_n + d_n - c) over the items of one order.
+// rho(c) += sum_n W(q_n + d_n - c) over the items of one order.  The
+// displacement of slot a is d[a], or d[gsrc[a]] when it was left in the
+// previous order (gsrc: this order's slots to that order's); then dcopy
+// receives it in this order.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, long long P,
+__global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
+                                                      const unsigned* __restrict__ gsrc,
+                                                      T* __restrict__ dcopy, long long P,
                                                       int lp, Grid<T> g, Layout L, Items it,
                                                       T* __restrict__ rho, T* __restrict__ zh,
                                                       T* __restrict__ halo) {
@@ -723,7 +745,13 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d, l
   for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
     long long a;
     ok[k] = item_slot(m, it, k, lp, a, idx[k]);
-    if (ok[k]) pk::load3(d, P, a, dsp[k]);
+    if (!ok[k]) continue;
+    pk::load3(d, P, gsrc ? static_cast<long long>(gsrc[a]) : a, dsp[k]);
+    if (dcopy) {
+      dcopy[a] = dsp[k][0];
+      dcopy[P + a] = dsp[k][1];
+      dcopy[2 * P + a] = dsp[k][2];
+    }
   }
   zero_window(acc, 1);
   const typename A::Scale sc = A::scale_for(1.0);  // weights are at most 1
@@ -800,12 +828,14 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
 // Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
 // state goes to (dn, pn) in this order with its block key and rank on grid L
 // (no keys when count is null: a replay into an order already recorded).
+// The momentum of slot a is p[a], or p[pinv[a]] when the momenta were left
+// in the previous order (pinv: this order's slots to that order's).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_step_b(
-    const T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ g, long long M,
-    T kick, T drift, long long P, int lp, Grid<T> gr, Layout L, Items it, T* __restrict__ dn,
-    T* __restrict__ pn, unsigned* __restrict__ count, unsigned* __restrict__ key,
-    unsigned* __restrict__ rank) {
+    const T* __restrict__ d, const T* __restrict__ p, const unsigned* __restrict__ pinv,
+    const T* __restrict__ g, long long M, T kick, T drift, long long P, int lp, Grid<T> gr,
+    Layout L, Items it, T* __restrict__ dn, T* __restrict__ pn, unsigned* __restrict__ count,
+    unsigned* __restrict__ key, unsigned* __restrict__ rank) {
   __shared__ T lds[3 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
@@ -819,7 +849,7 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
     ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
     if (!ok[k]) continue;
     pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(p, P, a[k], mom[k]);
+    pk::load3(p, P, pinv ? static_cast<long long>(pinv[a[k]]) : a[k], mom[k]);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();

@@ -139,6 +139,7 @@ class Engine final : public EngineBase {
     bcount_ = c.take<uint32_t>(std::max(nbm_, nbd_));
     bkey_ = c.take<uint32_t>(P_);
     brank_ = c.take<uint32_t>(P_);
+    pinv_ = c.take<uint32_t>(P_);
     bsums_ = c.take<uint2>(1024);
     // halos of the paints (blocks.h): the x/y staging, one slot of
     // nf x kHaloXY values per work item (three fields on the mesh orders, one
@@ -379,7 +380,7 @@ class Engine final : public EngineBase {
     force_from_density(gtape_);         // adds the z halo left in zh_
     fill(tmpp_, T(0), 3 * P_);
     bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-        tmpd_, tmpp_, gtape_, M_, T(1), T(0), P_, lp_, gmesh(), Lm_,
+        tmpd_, tmpp_, nullptr, gtape_, M_, T(1), T(0), P_, lp_, gmesh(), Lm_,
         items(mesh_order(0), dids_), dbar2_, pbar2_, nullptr, nullptr, nullptr);
     IC_LAUNCHED();
     T* F = static_cast<T*>(force);
@@ -654,14 +655,17 @@ class Engine final : public EngineBase {
 
   // rho = CIC density of the state in order o (positions d, ids id), its
   // z halo left in zh (ncells / 8 values) for the consumer; every cell of
-  // rho and zh is written here.
+  // rho and zh is written here.  With gsrc the positions are read as
+  // d[gsrc[a]] (left in the previous order) and stored in order o to dcopy.
   void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
-             const bk::Layout& L, T* rho, T* zh, long long ncells) {
+             const bk::Layout& L, T* rho, T* zh, long long ncells,
+             const unsigned* gsrc = nullptr, T* dcopy = nullptr) {
     zero_unowned(o, L, 1, bk::MPtrs<T>{{rho}}, zh);
     {
-      auto sc = timer_.scope("cic_paint", P_ * (3.0 * sizeT() + 4.0) + 2.0 * ncells * sizeT());
-      bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(d, P_, lp_, g, L,
-                                                                  items(o, id), rho, zh, hstage_);
+      auto sc = timer_.scope("cic_paint", P_ * ((gsrc ? 6.0 : 3.0) * sizeT() + (gsrc ? 8.0 : 4.0)) +
+                                               2.0 * ncells * sizeT());
+      bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(
+          d, gsrc, dcopy, P_, lp_, g, L, items(o, id), rho, zh, hstage_);
       IC_LAUNCHED();
     }
     halo_rows(o, L, 1, bk::MPtrs<T>{{rho}});
@@ -816,10 +820,25 @@ class Engine final : public EngineBase {
     chain_scatter(1, rhom_, T(1), nullptr, T(0), outs, sp, 3, zh_);
   }
 
-  // Force meshes of the state d_n (order n).
-  void force_mesh(int n, T* g) {
-    paint(dslot(n), mesh_order(n), ids(n), gmesh(), Lm_, rhom_, zh_, M_);
+  // Force meshes of the state d_n (order n).  With gsrc the positions are
+  // still in the previous order in tmpd_ (gsrc: order n's slots to that
+  // order's); the paint reads them through gsrc and stores d_n in its slot.
+  void force_mesh(int n, T* g, const unsigned* gsrc = nullptr) {
+    if (gsrc)
+      paint(tmpd_, mesh_order(n), ids(n), gmesh(), Lm_, rhom_, zh_, M_, gsrc, dslot(n));
+    else
+      paint(dslot(n), mesh_order(n), ids(n), gmesh(), Lm_, rhom_, zh_, M_);
     force_from_density(g);
+  }
+
+  // Whether state m must be complete in its own order after the forward's
+  // sort (positions and momenta in their slots): the last state, the
+  // checkpoints and the lightcone snapshots.  The other states leave the
+  // new positions and momenta where the step wrote them and move only the
+  // ids: the paint stores the positions in the new order as it reads them,
+  // and the next step reads the momenta through the new order's map back.
+  bool state_complete(int m) const {
+    return m == S_ || (K_ && m % K_ == 0) || snapshot_index(m) >= 0;
   }
 
   // Forward model.  The 2LPT state is sorted into block order 0; every
@@ -833,13 +852,34 @@ class Engine final : public EngineBase {
     scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), pslot(0)), 6, nullptr,
             ids(0), dest(-1));
     force_mesh(0, gslot(0));
+    // momenta of state n: pin, in order n or, with pinv, in order n - 1
+    const T* pin = pslot(0);
+    const unsigned* pinv = nullptr;
     for (int n = 0; n < S_; ++n) {
       zero_counts(nbm_);
-      step(n, true);
+      const bool complete = state_complete(n + 1);
+      // the new momenta go to a buffer the step does not read, and that a
+      // complete sort can move into pslot(n + 1) (never tmpp_ or pbar2_)
+      T* pout = pin == tmpp_ ? pbar2_ : tmpp_;
+      step(n, true, pin, pinv, pout);
       build_order(mesh_order(n + 1));
-      scatter(mesh_order(n + 1), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(n + 1), pslot(n + 1)),
-              6, ids(n), ids(n + 1), dest(n));
-      force_mesh(n + 1, gslot(n + 1));
+      if (complete) {
+        scatter(mesh_order(n + 1), state_ptrs(tmpd_, pout),
+                state_mptrs(dslot(n + 1), pslot(n + 1)), 6, ids(n), ids(n + 1), dest(n));
+        force_mesh(n + 1, gslot(n + 1));
+        pin = pslot(n + 1);
+        pinv = nullptr;
+      } else {
+        {
+          auto sc = timer_.scope("sort_scatter_ids", P_ * 24.0);
+          bk::k_scatter_ids<<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
+              bkey_, brank_, mesh_order(n + 1).start, ids(n), ids(n + 1), dest(n), pinv_, P_);
+          IC_LAUNCHED();
+        }
+        force_mesh(n + 1, gslot(n + 1), pinv_);
+        pin = pout;
+        pinv = pinv_;
+      }
       const int j = snapshot_index(n + 1);
       if (j >= 0) {
         // state n + 1 synchronised: p_{n+1/2} + K2_n F(d_{n+1})
@@ -903,15 +943,17 @@ class Engine final : public EngineBase {
     halo_rows(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}});  // z halo: in zhd_, read by the loss
   }
 
-  // Step n: readout of the forces at d_n, kick, drift into (tmpd_, tmpp_) in
+  // Step n: readout of the forces at d_n, kick, drift into (tmpd_, pout) in
   // order n, with the block keys and ranks of the new positions when keyed.
-  void step(int n, bool keyed) {
+  // The momenta are read from pin, through pinv when they were left in the
+  // previous order.
+  void step(int n, bool keyed, const T* pin, const unsigned* pinv, T* pout) {
     auto sc = timer_.scope(keyed ? "pm_step" : "pm_step_replay",
-                           P_ * (12.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+                           P_ * (12.0 * sizeT() + (pinv ? 16.0 : 12.0)) + 3.0 * M_ * sizeT());
     bk::k_step_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-        dslot(n), pslot(n), gslot(n), M_, static_cast<T>(co_.kick[n]), static_cast<T>(co_.Dr[n]),
-        P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_, tmpp_,
-        keyed ? bcount_ : nullptr, bkey_, brank_);
+        dslot(n), pin, pinv, gslot(n), M_, static_cast<T>(co_.kick[n]),
+        static_cast<T>(co_.Dr[n]), P_, lp_, gmesh(), Lm_, items(mesh_order(n), ids(n)), tmpd_,
+        pout, keyed ? bcount_ : nullptr, bkey_, brank_);
     IC_LAUNCHED();
   }
 
@@ -928,7 +970,7 @@ class Engine final : public EngineBase {
     const int last = std::min(c + K_ - 1, S_);
     for (int j = c; j < last; ++j) {
       force_mesh(j, gslot(j));
-      step(j, false);
+      step(j, false, pslot(j), nullptr, tmpp_);
       auto sc = timer_.scope("sort_replay", P_ * (12.0 * sizeT() + 4.0));
       bk::k_to_lattice<T><<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
           dest(j), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(j + 1), pslot(j + 1)), 6, P_);
@@ -1190,6 +1232,7 @@ class Engine final : public EngineBase {
   uint32_t *idtape_, *desttape_, *ostart_, *oistart_, *dstart_, *distart_, *dids_;
   uint2 *oitems_, *ditems_, *bsums_;
   uint32_t *bcount_, *bkey_, *brank_;
+  uint32_t* pinv_;  // the newest order's slots to the previous order's
   T* hstage_ = nullptr;
   T* zh_ = nullptr;
   T* zhd_ = nullptr;

@@ -34,6 +34,7 @@ SCOPES = {
     "k_data_adjoint_b": "data_adjoint",
     "k_paint_b": "cic_paint",
     "k_scatter": "sort_scatter",
+    "k_scatter_ids": "sort_scatter_ids",
     "k_gather_back": "sort_gather_back",
     "k_keys": "sort_keys",
     "k_r2c_z": "fft_r2c_z",
