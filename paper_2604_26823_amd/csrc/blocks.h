@@ -373,9 +373,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter(
   dest[a] = s;
 }
 
-// The ids of slot a to slot s = start[key[a]] + rank[a] of the new order,
-// dest[a] = s, and inv[s] = a: the new order's map back to this one, through
-// which the next kernels read the state left in this order.
+// The ids of slot a (a itself when ids_src is null) to slot
+// s = start[key[a]] + rank[a] of the new order, dest[a] = s, and inv[s] = a:
+// the new order's map back to this one, through which the next kernels read
+// the state left in this order.
 static __global__ __launch_bounds__(kThreads) void k_scatter_ids(
     const unsigned* __restrict__ key, const unsigned* __restrict__ rank,
     const unsigned* __restrict__ start, const unsigned* __restrict__ ids_src,
@@ -383,7 +384,7 @@ static __global__ __launch_bounds__(kThreads) void k_scatter_ids(
     long long P) {
   const long long a = blockIdx.x * (long long)kThreads + threadIdx.x;
   if (a >= P) return;
-  const unsigned id = ids_src[a];
+  const unsigned id = ids_src ? ids_src[a] : static_cast<unsigned>(a);
   const unsigned s = start[key[a]] + rank[a];
   ids_dst[s] = id;
   inv[s] = static_cast<unsigned>(a);
@@ -953,14 +954,17 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
   }
 }
 
-// Last kick (readout of g at d), p updated in place; then the key and rank
-// of the redshift-space position on the data grid (layout Ld).
+// Last kick (readout of g at d) of the momenta p into pout in this order,
+// then the key and rank of the redshift-space position on the data grid
+// (layout Ld).  The momentum of slot a is p[a] (pout may then be p: each
+// slot is read and written by one thread), or p[pinv[a]] when the momenta
+// were left in the previous order (pout apart from p).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_final_b(
-    const T* __restrict__ d, T* __restrict__ p, const T* __restrict__ g, long long M, T kick,
-    long long P, int lp, Grid<T> gm, Layout L, Items it, pk::Rsd<T> rsd, Grid<T> gd,
-    Layout Ld, unsigned* __restrict__ count, unsigned* __restrict__ key,
-    unsigned* __restrict__ rank) {
+    const T* __restrict__ d, const T* p, const unsigned* __restrict__ pinv, T* pout,
+    const T* __restrict__ g, long long M, T kick, long long P, int lp, Grid<T> gm, Layout L,
+    Items it, pk::Rsd<T> rsd, Grid<T> gd, Layout Ld, unsigned* __restrict__ count,
+    unsigned* __restrict__ key, unsigned* __restrict__ rank) {
   __shared__ T lds[3 * kWin];
   Item m;
   if (!item_of<true>(it, L, m)) return;
@@ -974,7 +978,7 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
     ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
     if (!ok[k]) continue;
     pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(p, P, a[k], mom[k]);
+    pk::load3(p, P, pinv ? static_cast<long long>(pinv[a[k]]) : a[k], mom[k]);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
   __syncthreads();
@@ -993,7 +997,7 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       mom[k][q] += kick * F[q];
-      p[q * P + a[k]] = mom[k][q];
+      pout[q * P + a[k]] = mom[k][q];
     }
     pk::rsd_shift(rsd, idx[k], dsp[k], mom[k], ds);
     Stencil<T> s2 = pk::stencil(idx[k], gd.ratio, ds, gd.inv_cell, gd.cell);

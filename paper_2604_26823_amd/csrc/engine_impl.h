@@ -620,6 +620,17 @@ class Engine final : public EngineBase {
     IC_LAUNCHED();
   }
 
+  // The ids alone to the order o (keys and ranks in bkey_ / brank_; ids_src
+  // null means the lattice order), the destinations to dst_slots, and pinv_
+  // = o's slots to the source order's.
+  void scatter_ids(const Order& o, const unsigned* ids_src, unsigned* ids_dst,
+                   unsigned* dst_slots) {
+    auto sc = timer_.scope("sort_scatter_ids", P_ * 24.0);
+    bk::k_scatter_ids<<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
+        bkey_, brank_, o.start, ids_src, ids_dst, dst_slots, pinv_, P_);
+    IC_LAUNCHED();
+  }
+
   // Keys and ranks of displacements d (lattice order) on grid g.
   void keys_lattice(const T* d, const pk::Grid<T>& g, const bk::Layout& L, unsigned nb) {
     zero_counts(nb);
@@ -832,14 +843,13 @@ class Engine final : public EngineBase {
   }
 
   // Whether state m must be complete in its own order after the forward's
-  // sort (positions and momenta in their slots): the last state, the
-  // checkpoints and the lightcone snapshots.  The other states leave the
-  // new positions and momenta where the step wrote them and move only the
-  // ids: the paint stores the positions in the new order as it reads them,
-  // and the next step reads the momenta through the new order's map back.
-  bool state_complete(int m) const {
-    return m == S_ || (K_ && m % K_ == 0) || snapshot_index(m) >= 0;
-  }
+  // sort (positions and momenta in their slots): the checkpoints and the
+  // lightcone snapshots.  The other states leave the new positions and
+  // momenta where the step (or the 2LPT) wrote them and move only the ids:
+  // the paint stores the positions in the new order as it reads them, and
+  // the next step (or the last kick) reads the momenta through the new
+  // order's map back.
+  bool state_complete(int m) const { return (K_ && m % K_ == 0) || snapshot_index(m) >= 0; }
 
   // Forward model.  The 2LPT state is sorted into block order 0; every
   // step reads the forces of its order, kicks and drifts, and sorts the new
@@ -849,12 +859,20 @@ class Engine final : public EngineBase {
     lpt(s, tmpd_, tmpp_);
     keys_lattice(tmpd_, gmesh(), Lm_, nbm_);
     build_order(mesh_order(0));
-    scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), pslot(0)), 6, nullptr,
-            ids(0), dest(-1));
-    force_mesh(0, gslot(0));
-    // momenta of state n: pin, in order n or, with pinv, in order n - 1
+    // momenta of state n: pin, in order n or, with pinv, in order n - 1 (the
+    // lattice order for n = 0)
     const T* pin = pslot(0);
     const unsigned* pinv = nullptr;
+    if (state_complete(0)) {
+      scatter(mesh_order(0), state_ptrs(tmpd_, tmpp_), state_mptrs(dslot(0), pslot(0)), 6,
+              nullptr, ids(0), dest(-1));
+      force_mesh(0, gslot(0));
+    } else {
+      scatter_ids(mesh_order(0), nullptr, ids(0), dest(-1));
+      force_mesh(0, gslot(0), pinv_);
+      pin = tmpp_;
+      pinv = pinv_;
+    }
     for (int n = 0; n < S_; ++n) {
       zero_counts(nbm_);
       const bool complete = state_complete(n + 1);
@@ -870,12 +888,7 @@ class Engine final : public EngineBase {
         pin = pslot(n + 1);
         pinv = nullptr;
       } else {
-        {
-          auto sc = timer_.scope("sort_scatter_ids", P_ * 24.0);
-          bk::k_scatter_ids<<<grid_for(P_, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
-              bkey_, brank_, mesh_order(n + 1).start, ids(n), ids(n + 1), dest(n), pinv_, P_);
-          IC_LAUNCHED();
-        }
+        scatter_ids(mesh_order(n + 1), ids(n), ids(n + 1), dest(n));
         force_mesh(n + 1, gslot(n + 1), pinv_);
         pin = pout;
         pinv = pinv_;
@@ -894,9 +907,12 @@ class Engine final : public EngineBase {
     zero_counts(nbd_);
     {
       auto sc = timer_.scope("final_kick", P_ * (9.0 * sizeT() + 12.0) + 3.0 * M_ * sizeT());
+      // the final momenta go to pslot(S) in order S (in place when state S
+      // is complete; else pin, in tmpp_ or pbar2_, is read through pinv)
       bk::k_final_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-          dslot(S_), pslot(S_), gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_, gmesh(),
-          Lm_, items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_, brank_);
+          dslot(S_), pin, pinv, pslot(S_), gslot(S_), M_, static_cast<T>(co_.kick[S_]), P_, lp_,
+          gmesh(), Lm_, items(mesh_order(S_), ids(S_)), rsd(), gdata(), Ld_, bcount_, bkey_,
+          brank_);
       IC_LAUNCHED();
     }
     const T* fd = dslot(S_);
