@@ -5,9 +5,13 @@
 // corners of its stencil fall inside that block extended by one cell on the
 // upper side: a fixed 9^3-cell window.  After each drift the particles are
 // counting-sorted by block (per-block counts with wavefront- or workgroup-aggregated
-// atomics, an exclusive scan, a scatter of the state into block order), and
-// every paint and readout then runs over work items of at most 1024 particles
-// of one block, with the block's window in LDS:
+// atomics, an exclusive scan, then a scatter of the ids alone, with the new
+// order's map back to the old: the density paint reads the new positions
+// through that map and stores them in the new order, the next step reads the
+// momenta through it; states that must be complete in their order move
+// positions and momenta too), and every paint and readout then runs over work
+// items of at most 1024 particles of one block, with the block's window in
+// LDS:
 //   * paints accumulate in LDS windows (FP64 adds for FP64 grids, exact
 //     64-bit fixed-point adds for FP32 grids, see WinAcc); a block's only
 //     item stores its 8^3 own cells (the items of a block with several add
