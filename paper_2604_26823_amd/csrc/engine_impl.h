@@ -932,9 +932,9 @@ class Engine final : public EngineBase {
         auto sc = timer_.scope("lc_crossing",
                                P_ * ((6.0 * lc_steps_.size() + 15.0) * sizeT() +
                                      4.0 * (lc_steps_.size() + 1)));
-        lk::k_lightcone<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-            dslot(S_), pslot(S_), ids(S_), snapinv_, snap_, lcgeo_, rsd(), tmpd_, tmpp_, dbar2_,
-            P_, lp_);
+        IC_LK_LAUNCH(k_lightcone, T, lcgeo_, grid_for(P_, kThreads), kThreads, st_, dslot(S_),
+                     pslot(S_), ids(S_), snapinv_, snap_, lcgeo_, rsd(), tmpd_, tmpp_, dbar2_,
+                     P_, lp_);
         IC_LAUNCHED();
       }
       zero_counts(nbd_);
@@ -1077,9 +1077,9 @@ class Engine final : public EngineBase {
       // snapshots into snapbar_ (the final state is still in its slots: no
       // segment has been replayed yet)
       auto sc = timer_.scope("lc_adjoint", P_ * (12.0 * lc_steps_.size() + 16.0) * sizeT());
-      lk::k_lightcone_adjoint<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-          dslot(S_), pslot(S_), ids(S_), snapinv_, dest(S_), snap_, lcgeo_, rsd(), dbar_, pbar_,
-          snapbar_, P_, lp_);
+      IC_LK_LAUNCH(k_lightcone_adjoint, T, lcgeo_, grid_for(P_, kThreads), kThreads, st_,
+                   dslot(S_), pslot(S_), ids(S_), snapinv_, dest(S_), snap_, lcgeo_, rsd(), dbar_,
+                   pbar_, snapbar_, P_, lp_);
       IC_LAUNCHED();
     }
     // rho_bar = delta_bar / nbar with delta_bar = -sum_j Op_g_j[g_bar_j].

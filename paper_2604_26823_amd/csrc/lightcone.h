@@ -66,28 +66,44 @@ __device__ __forceinline__ double scale_factor(const LcTable& t, double r, bool&
   return h00 * t.a[k] + h10 * t.h * t.slope[k] + h01 * t.a[k + 1] + h11 * t.h * t.slope[k + 1];
 }
 
-// Bracket of a: lower snapshot j (the last with a_snap[j] <= a, at most J-2)
-// and the weight t of snapshot j + 1.
-__device__ __forceinline__ void bracket(const LcGeo& g, double a, int& j, double& t) {
+// The per-particle arrays below are indexed only by compile-time indices
+// (NJ = the snapshot count, the fixed-point iterations unrolled up to KM >=
+// iterations, KM = 4 or kMaxIter): a run-time index into them would put them
+// in scratch memory.
+
+// Bracket of a: lower snapshot j (the last with a_snap[j] <= a, at most
+// NJ - 2), the weight t of snapshot j + 1 and the bracket's span in a.
+template <int NJ>
+__device__ __forceinline__ void bracket(const LcGeo& g, double a, int& j, double& t,
+                                        double& span) {
   j = 0;
-  for (int i = 1; i < g.J - 1; ++i)
-    if (g.a_snap[i] <= a) j = i;
-  t = (a - g.a_snap[j]) / (g.a_snap[j + 1] - g.a_snap[j]);
+  double lo = g.a_snap[0], hi = g.a_snap[1];
+#pragma unroll
+  for (int i = 1; i < NJ - 1; ++i)
+    if (g.a_snap[i] <= a) {
+      j = i;
+      lo = g.a_snap[i];
+      hi = g.a_snap[i + 1];
+    }
+  span = hi - lo;
+  t = (a - lo) / span;
 }
 
 // One particle's snapshot states (FP64 copies).
+template <int NJ>
 struct Snaps {
-  double d[kMaxSnap][3];
-  double p[kMaxSnap][3];
+  double d[NJ][3];
+  double p[NJ][3];
 };
 
 // Snapshot j of final slot a sits at slot inv[j P + a] of its own order.
-template <typename T>
-__device__ __forceinline__ void load_snaps(const LcGeo& g, const T* __restrict__ snap,
-                                           const T* __restrict__ dS, const T* __restrict__ pS,
+template <typename T, int NJ>
+__device__ __forceinline__ void load_snaps(const T* __restrict__ snap, const T* __restrict__ dS,
+                                           const T* __restrict__ pS,
                                            const unsigned* __restrict__ inv, long long P,
-                                           long long a, Snaps& s) {
-  for (int j = 0; j + 1 < g.J; ++j) {
+                                           long long a, Snaps<NJ>& s) {
+#pragma unroll
+  for (int j = 0; j + 1 < NJ; ++j) {
     const T* b = snap + (long long)j * 6 * P;
     const long long sj = inv[(long long)j * P + a];
 #pragma unroll
@@ -98,43 +114,85 @@ __device__ __forceinline__ void load_snaps(const LcGeo& g, const T* __restrict__
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    s.d[g.J - 1][q] = static_cast<double>(dS[q * P + a]);
-    s.p[g.J - 1][q] = static_cast<double>(pS[q * P + a]);
+    s.d[NJ - 1][q] = static_cast<double>(dS[q * P + a]);
+    s.p[NJ - 1][q] = static_cast<double>(pS[q * P + a]);
+  }
+}
+
+// x[j] += (1 - t) v, x[j + 1] += t v for the bracket j of a run-time value
+// (every x[i] is updated with a selected weight, so that no update is
+// indexed by j).
+template <int NJ>
+__device__ __forceinline__ void add_bracket(double (&x)[NJ][3], int j, double t,
+                                            const double v[3]) {
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const double w = (i == j ? 1.0 - t : 0.0) + (i == j + 1 ? t : 0.0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[i][q] += w * v[q];
   }
 }
 
 // Interpolated displacement (as T, the value the line of sight sees) and
-// the slopes d x / d a, d p / d a of the bracket.
-template <typename T>
-__device__ __forceinline__ void interp(const LcGeo& g, const Snaps& s, double a, T d[3],
-                                       double p[3], double dd[3], double dp[3]) {
-  int j;
-  double t;
-  bracket(g, a, j, t);
-  const double span = g.a_snap[j + 1] - g.a_snap[j];
+// the slopes d x / d a, d p / d a of the bracket; j, t: the bracket.
+template <typename T, int NJ>
+__device__ __forceinline__ void interp(const LcGeo& g, const Snaps<NJ>& s, double a, T d[3],
+                                       double p[3], double dd[3], double dp[3], int& j,
+                                       double& t) {
+  double span;
+  bracket<NJ>(g, a, j, t, span);
+  double d0[3], d1[3], p0[3], p1[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    d[q] = static_cast<T>((1.0 - t) * s.d[j][q] + t * s.d[j + 1][q]);
-    p[q] = (1.0 - t) * s.p[j][q] + t * s.p[j + 1][q];
-    dd[q] = (s.d[j + 1][q] - s.d[j][q]) / span;
-    dp[q] = (s.p[j + 1][q] - s.p[j][q]) / span;
+    d0[q] = s.d[0][q];
+    d1[q] = s.d[1][q];
+    p0[q] = s.p[0][q];
+    p1[q] = s.p[1][q];
+  }
+#pragma unroll
+  for (int i = 1; i + 1 < NJ; ++i)
+    if (j == i) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        d0[q] = s.d[i][q];
+        d1[q] = s.d[i + 1][q];
+        p0[q] = s.p[i][q];
+        p1[q] = s.p[i + 1][q];
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    d[q] = static_cast<T>((1.0 - t) * d0[q] + t * d1[q]);
+    p[q] = (1.0 - t) * p0[q] + t * p1[q];
+    dd[q] = (d1[q] - d0[q]) / span;
+    dp[q] = (p1[q] - p0[q]) / span;
   }
 }
 
-// Scale factors a^(0) = a_final, a^(k) = A(r(a^(k-1))), k <= iterations;
-// unc[k]: a^(k) was not clamped.
-template <typename T>
-__device__ __forceinline__ void crossing(const LcGeo& g, const pk::Rsd<T>& rsd, const int idx[3],
-                                         const Snaps& s, double* av, bool* unc) {
-  av[0] = g.a_snap[g.J - 1];
-  unc[0] = false;
-  for (int k = 1; k <= g.iterations; ++k) {
+// Scale factors a^(0) = a_final, a^(k) = A(r(a^(k-1))), k <= iterations
+// (<= KM); bit k of unc: a^(k) was not clamped.  Returns a^(iterations).
+template <typename T, int NJ, int KM>
+__device__ __forceinline__ double crossing(const LcGeo& g, const pk::Rsd<T>& rsd,
+                                           const int idx[3], const Snaps<NJ>& s,
+                                           double (&av)[KM + 1], unsigned& unc) {
+  av[0] = g.a_snap[NJ - 1];
+  unc = 0u;
+  double last = av[0];
+#pragma unroll
+  for (int k = 1; k <= KM; ++k) {
+    av[k] = last;
+    if (k > g.iterations) continue;
     T d[3], u[3], dist;
-    double p[3], dd[3], dp[3];
-    interp<T>(g, s, av[k - 1], d, p, dd, dp);
+    double p[3], dd[3], dp[3], t;
+    int j;
+    interp<T, NJ>(g, s, av[k - 1], d, p, dd, dp, j, t);
     pk::los(rsd, idx, d, u, dist);
-    av[k] = scale_factor(g.tab, static_cast<double>(dist), unc[k]);
+    bool inside;
+    av[k] = scale_factor(g.tab, static_cast<double>(dist), inside);
+    if (inside) unc |= 1u << k;
+    last = av[k];
   }
+  return last;
 }
 
 // Kick-synchronised snapshot of state n, in its own block order (ids =
@@ -180,7 +238,7 @@ static __global__ __launch_bounds__(256) void k_snapshot_slots(const unsigned* _
 // Lightcone state of every particle of the final order: displacement lcd,
 // momentum scaled to the final RSD factor lcp, and the redshift-space
 // displacement ds (for the data-grid keys).
-template <typename T>
+template <typename T, int NJ, int KM>
 __global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, const T* __restrict__ pS,
                                                    const unsigned* __restrict__ ids,
                                                    const unsigned* __restrict__ inv,
@@ -192,15 +250,15 @@ __global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, con
        a += (long long)gridDim.x * blockDim.x) {
     int idx[3];
     pk::lattice(static_cast<long long>(ids[a]), lp, idx);
-    Snaps s;
-    load_snaps<T>(g, snap, dS, pS, inv, P, a, s);
-    double av[kMaxIter + 1];
-    bool unc[kMaxIter + 1];
-    crossing<T>(g, rsd, idx, s, av, unc);
-    const double ai = av[g.iterations];
+    Snaps<NJ> s;
+    load_snaps<T, NJ>(snap, dS, pS, inv, P, a, s);
+    double av[KM + 1];
+    unsigned unc;
+    const double ai = crossing<T, NJ, KM>(g, rsd, idx, s, av, unc);
     T d[3];
-    double p[3], dd[3], dp[3];
-    interp<T>(g, s, ai, d, p, dd, dp);
+    double p[3], dd[3], dp[3], t;
+    int j;
+    interp<T, NJ>(g, s, ai, d, p, dd, dp, j, t);
     const double k = 1.0 / (ai * ai * hubble_E(ai, g.om) * g.c_final);
     T pe[3], out[3];
 #pragma unroll
@@ -219,7 +277,7 @@ __global__ __launch_bounds__(256) void k_lightcone(const T* __restrict__ dS, con
 // order on entry (slot dest[a] for final-order slot a), of the final state
 // (d_S, p_S) on exit, in place; snapbar: cotangents of the other snapshots,
 // each in its snapshot's order (every entry written).
-template <typename T>
+template <typename T, int NJ, int KM>
 __global__ __launch_bounds__(256) void k_lightcone_adjoint(
     const T* __restrict__ dS, const T* __restrict__ pS, const unsigned* __restrict__ ids,
     const unsigned* __restrict__ inv, const unsigned* __restrict__ dest,
@@ -230,20 +288,21 @@ __global__ __launch_bounds__(256) void k_lightcone_adjoint(
     const long long ad = dest[a];
     int idx[3];
     pk::lattice(static_cast<long long>(ids[a]), lp, idx);
-    Snaps s;
-    load_snaps<T>(g, snap, dS, pS, inv, P, a, s);
-    double av[kMaxIter + 1];
-    bool unc[kMaxIter + 1];
-    crossing<T>(g, rsd, idx, s, av, unc);
-    double sd[kMaxSnap][3], sp[kMaxSnap][3];
-    for (int j = 0; j < g.J; ++j)
+    Snaps<NJ> s;
+    load_snaps<T, NJ>(snap, dS, pS, inv, P, a, s);
+    double av[KM + 1];
+    unsigned unc;
+    const double ai = crossing<T, NJ, KM>(g, rsd, idx, s, av, unc);
+    double sd[NJ][3], sp[NJ][3];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int q = 0; q < 3; ++q) sd[j][q] = sp[j][q] = 0.0;
     const int K = g.iterations;
-    const double ai = av[K];
     T d[3];
-    double p[3], dd[3], dp[3];
-    interp<T>(g, s, ai, d, p, dd, dp);
+    double p[3], dd[3], dp[3], t;
+    int j;
+    interp<T, NJ>(g, s, ai, d, p, dd, dp, j, t);
     // lcp = k(a) p with k = c(a) / c_final, c = 1 / (a^2 E)
     const double E = hubble_E(ai, g.om);
     const double k = 1.0 / (ai * ai * E * g.c_final);
@@ -257,34 +316,29 @@ __global__ __launch_bounds__(256) void k_lightcone_adjoint(
       pb[q] = k * pe;
       abar += dk * p[q] * pe + xb[q] * dd[q] + pb[q] * dp[q];
     }
-    int j;
-    double t;
-    bracket(g, ai, j, t);
+    add_bracket<NJ>(sd, j, t, xb);
+    add_bracket<NJ>(sp, j, t, pb);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      sd[j][q] += (1.0 - t) * xb[q];
-      sp[j][q] += (1.0 - t) * pb[q];
-      sd[j + 1][q] += t * xb[q];
-      sp[j + 1][q] += t * pb[q];
-    }
-    for (int it = K; it >= 1; --it) {
+    for (int it = KM; it >= 1; --it) {
+      if (it > K) continue;
       const double ak = av[it];
-      const double rbar = unc[it] ? abar * (-ak * ak * hubble_E(ak, g.om) / kCOverH0) : 0.0;
+      const double rbar = ((unc >> it) & 1u) ? abar * (-ak * ak * hubble_E(ak, g.om) / kCOverH0)
+                                             : 0.0;
       T dk3[3], u[3], dist;
       double pk3[3], ddk[3], dpk[3];
-      interp<T>(g, s, av[it - 1], dk3, pk3, ddk, dpk);
+      interp<T, NJ>(g, s, av[it - 1], dk3, pk3, ddk, dpk, j, t);
       pk::los(rsd, idx, dk3, u, dist);
-      bracket(g, av[it - 1], j, t);
+      double rd[3];
       abar = 0.0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const double rd = rbar * static_cast<double>(u[q]);
-        sd[j][q] += (1.0 - t) * rd;
-        sd[j + 1][q] += t * rd;
-        abar += rd * ddk[q];
+        rd[q] = rbar * static_cast<double>(u[q]);
+        abar += rd[q] * ddk[q];
       }
+      add_bracket<NJ>(sd, j, t, rd);
     }
-    for (int jj = 0; jj + 1 < g.J; ++jj) {
+#pragma unroll
+    for (int jj = 0; jj + 1 < NJ; ++jj) {
       T* b = snapbar + (long long)jj * 6 * P;
       const long long sj = inv[(long long)jj * P + a];
 #pragma unroll
@@ -295,11 +349,31 @@ __global__ __launch_bounds__(256) void k_lightcone_adjoint(
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      dbar[q * P + ad] = static_cast<T>(sd[g.J - 1][q]);
-      pbar[q * P + ad] = static_cast<T>(sp[g.J - 1][q]);
+      dbar[q * P + ad] = static_cast<T>(sd[NJ - 1][q]);
+      pbar[q * P + ad] = static_cast<T>(sp[NJ - 1][q]);
     }
   }
 }
+
+// Launch of a lightcone kernel K<T, NJ, KM> for NJ = g.J snapshots (2 to 4)
+// and KM = 4 when g.iterations <= 4 (the unrolled iterates stay in
+// registers), else kMaxIter.
+#define IC_LK_LAUNCH_KM(K, T, NJ, g, grid, threads, stream, ...)                            \
+  do {                                                                                      \
+    if ((g).iterations <= 4)                                                                \
+      ::ic::lk::K<T, NJ, 4><<<(grid), (threads), 0, (stream)>>>(__VA_ARGS__);               \
+    else                                                                                    \
+      ::ic::lk::K<T, NJ, ::ic::lk::kMaxIter><<<(grid), (threads), 0, (stream)>>>(__VA_ARGS__); \
+  } while (0)
+#define IC_LK_LAUNCH(K, T, g, grid, threads, stream, ...)                                   \
+  do {                                                                                      \
+    switch ((g).J) {                                                                        \
+      case 2: IC_LK_LAUNCH_KM(K, T, 2, g, grid, threads, stream, __VA_ARGS__); break;       \
+      case 3: IC_LK_LAUNCH_KM(K, T, 3, g, grid, threads, stream, __VA_ARGS__); break;       \
+      case 4: IC_LK_LAUNCH_KM(K, T, 4, g, grid, threads, stream, __VA_ARGS__); break;       \
+      default: throw ::ic::ApiError(IC_ERR_INVALID_ARG, "lightcone snapshots must be 2 to 4"); \
+    }                                                                                       \
+  } while (0)
 
 // Snapshot cotangents (in the snapshot's order) into the reverse sweep:
 // dbar[t] += cd sd[a], pbar[t] += cp sp[a] with t = dest[a] (the slot in the
