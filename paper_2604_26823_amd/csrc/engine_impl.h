@@ -853,8 +853,10 @@ class Engine final : public EngineBase {
 
   // Forward model.  The 2LPT state is sorted into block order 0; every
   // step reads the forces of its order, kicks and drifts, and sorts the new
-  // state into the next order (tapes: d_n, ids and dest per order); the last
-  // kick ends in order S, which the data paint re-sorts on the data grid.
+  // state into the next order (tapes: d_n, ids and dest per order; see
+  // state_complete for which states move positions and momenta in the sort
+  // and which only their ids); the last kick ends in order S, which the
+  // data paint re-sorts on the data grid.
   void run_forward(const T* s) {
     lpt(s, tmpd_, tmpp_);
     keys_lattice(tmpd_, gmesh(), Lm_, nbm_);
