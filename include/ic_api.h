@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define IC_ABI_VERSION 5
+#define IC_ABI_VERSION 6
 
 #define IC_OK 0
 #define IC_ERR_INVALID_ARG (-1)
@@ -147,6 +147,19 @@ typedef struct ic_problem {
                             [lc_a[0], a_final], sets where it is painted and its RSD
                             factor 1/(a_i^2 E(a_i)).  Distances: box-wrapped positions,
                             flat-cosmology comoving distance with c/H0 = 2997.92458 */
+  int32_t deterministic; /* 1: every result is a function of the inputs alone, bit for bit
+                            from run to run.  The three cloud-in-cell paints (density,
+                            data grid, the adjoint's momentum-cotangent paint) then sum
+                            each cell's contributions as 64-bit integers with one
+                            power-of-two scale per paint, chosen from the largest
+                            contribution so that no sum of n_part^3 of them can
+                            overflow, and add them with integer atomics, whose order
+                            cannot change the sum; rounding each contribution to that
+                            scale (an absolute error of at most 2^-62 n_part^3 times the
+                            largest contribution: 2^-38 of it at n_part = 256) is the
+                            mode's only numerical change.
+                            0 (default): the paints accumulate in the faster per-block
+                            order, whose floating-point rounding can differ between runs */
 } ic_problem;
 
 typedef struct ic_loss_terms {

@@ -48,6 +48,7 @@ class IcProblem(ctypes.Structure):
         ("bias_k", ctypes.c_double), ("loss_kind", ctypes.c_int32),
         ("project_steps", ctypes.c_int32), ("lc_n", ctypes.c_int32),
         ("lc_iterations", ctypes.c_int32), ("lc_a", ctypes.c_double * 4),
+        ("deterministic", ctypes.c_int32),
     ]
 
 

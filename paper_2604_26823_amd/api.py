@@ -15,7 +15,8 @@ from ._lib import IcLbfgsInfo, IcLossTerms, IcProblem, IcRomInfo
 PROBLEM_KEYS = ["n_part", "n_mesh", "n_steps", "box", "a_init", "a_final", "omega_m", "h",
                 "n_s", "sigma8", "bias", "nbar", "r_min", "prior_weight", "lbfgs_m",
                 "max_trials", "eps_max", "armijo_c1", "s_th", "rom_nbins", "tape_forces", "ckpt_every",
-                "rom_kmin", "seed", "bias_alpha", "bias_delta_th", "bias_k", "project_steps"]
+                "rom_kmin", "seed", "bias_alpha", "bias_delta_th", "bias_k", "project_steps",
+                "deterministic"]
 
 
 def make_problem(cfg):

@@ -38,6 +38,8 @@
 // order 0 back to the lattice order).
 #pragma once
 
+#include <type_traits>
+
 #include "particles.h"
 
 namespace ic {
@@ -530,8 +532,7 @@ struct WinAcc {
   __device__ static void add(Cell* c, double v, const Scale&) { atomicAdd(c, v); }
   __device__ static double get(Cell c, const Scale&) { return c; }
 };
-template <>
-struct WinAcc<float> {
+struct FixAcc {
   using Cell = unsigned long long;
   struct Scale {
     double s, inv;
@@ -543,6 +544,16 @@ struct WinAcc<float> {
     frexp(amax, &k);
     return Scale{ldexp(1.0, 52 - k), ldexp(1.0, k - 52)};
   }
+  // The scale of a deterministic paint, one for the whole paint: amax 2^e
+  // 2^lpc < 2^62, so that a cell may receive one contribution from each of
+  // the 2^lpc particles (a particle adds to a cell at most once) without
+  // overflow; the rounding of a contribution is at most 2^(lpc - 62) amax.
+  __device__ static Scale scale_det(double amax, int lpc) {
+    if (!(amax > 0.0)) return Scale{1.0, 1.0};
+    int k;
+    frexp(amax, &k);
+    return Scale{ldexp(1.0, 62 - lpc - k), ldexp(1.0, k + lpc - 62)};
+  }
   __device__ static void add(Cell* c, double v, const Scale& sc) {
     atomicAdd(c, static_cast<unsigned long long>(__double2ll_rn(v * sc.s)));
   }
@@ -550,6 +561,22 @@ struct WinAcc<float> {
     return static_cast<double>(static_cast<long long>(c)) * sc.inv;
   }
 };
+template <>
+struct WinAcc<float> : FixAcc {};
+
+// Window accumulator of a paint: WinAcc<T>, or fixed point in deterministic
+// mode (DET) for both precisions.
+template <typename T, bool DET>
+using PaintAcc = typename std::conditional<DET, FixAcc, WinAcc<T>>::type;
+
+// Largest |contribution| a deterministic paint's scale is chosen for: the
+// CIC weights (at most 1) times coef times the largest |v| (vmax, device;
+// null for a density paint).  Computed the same way by the paint and by
+// k_det_to_field.
+template <typename T>
+__device__ __forceinline__ double det_amax(const double* vmax, T coef) {
+  return vmax ? fabs(static_cast<double>(coef * static_cast<T>(*vmax))) : 1.0;
+}
 
 template <typename C>
 __device__ __forceinline__ void zero_window(C* acc, int nf) {
@@ -661,6 +688,47 @@ __global__ __launch_bounds__(kThreads) void k_zero_unowned(const unsigned* __res
   }
 }
 
+// Output of a paint in deterministic mode: the integer field det (nf fields
+// of ncells, zeroed before the paint), the device maximum |v| the scale is
+// chosen for (null for a density paint) and lpc = log2 of the particle count.
+struct DetOut {
+  unsigned long long* det;
+  const double* vmax;
+  long long ncells;
+  int lpc;
+};
+
+// Flush of a deterministic paint: every window cell's integer sum added
+// with a 64-bit integer atomic into det (nf fields of ncells, zeroed before
+// the paint).  Integer adds commute, so the result does not depend on the
+// order of the atomics nor on which particles share an item.
+__device__ __forceinline__ void flush_det(const Item& m, const Layout& L, const FixAcc::Cell* acc,
+                                          int nf, unsigned long long* __restrict__ det,
+                                          long long ncells) {
+  for (int k = threadIdx.x; k < kWin; k += kThreads) {
+    const long long c = win_cell(m.o, k, L);
+    for (int f = 0; f < nf; ++f) {
+      const unsigned long long v = acc[f * kWin + k];
+      if (v) atomicAdd(det + f * ncells + c, v);
+    }
+  }
+}
+
+// The fields of a deterministic paint: out_f[i] = det[f ncells + i] 2^-e with
+// the paint's scale (vmax, coef, lpc as given to the paint).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_det_to_field(const unsigned long long* __restrict__ det,
+                                                           int nf, long long ncells,
+                                                           const double* __restrict__ vmax,
+                                                           T coef, int lpc, MPtrs<T> out) {
+  const double inv = FixAcc::scale_det(det_amax<T>(vmax, coef), lpc).inv;
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < ncells;
+       i += (long long)gridDim.x * kThreads)
+    for (int f = 0; f < nf; ++f)
+      out.p[f][i] =
+          static_cast<T>(static_cast<double>(static_cast<long long>(det[f * ncells + i])) * inv);
+}
+
 // Cells that receive x/y halo values: those with x or y on a block's lowest
 // layer (x = 8 i: every y; y = 8 j: x not on such a layer).  They are
 // visited block face by block face, one wavefront per face: 2 nb^3 faces
@@ -731,15 +799,16 @@ __global__ __launch_bounds__(kThreads) void k_add_zh(T* __restrict__ rho, const 
 // rho(c) += sum_n W(q_n + d_n - c) over the items of one order.  The
 // displacement of slot a is d[a], or d[gsrc[a]] when it was left in the
 // previous order (gsrc: this order's slots to that order's); then dcopy
-// receives it in this order.
-template <typename T>
+// receives it in this order.  DET: the deterministic mode's output (dt)
+// instead of rho, zh and halo.
+template <typename T, bool DET>
 __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
                                                       const unsigned* __restrict__ gsrc,
                                                       T* __restrict__ dcopy, long long P,
                                                       int lp, Grid<T> g, Layout L, Items it,
                                                       T* __restrict__ rho, T* __restrict__ zh,
-                                                      T* __restrict__ halo) {
-  using A = WinAcc<T>;
+                                                      T* __restrict__ halo, DetOut dt) {
+  using A = PaintAcc<T, DET>;
   __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
@@ -759,7 +828,11 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
     }
   }
   zero_window(acc, 1);
-  const typename A::Scale sc = A::scale_for(1.0);  // weights are at most 1
+  typename A::Scale sc;  // weights are at most 1
+  if constexpr (DET)
+    sc = FixAcc::scale_det(1.0, dt.lpc);
+  else
+    sc = A::scale_for(1.0);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -770,12 +843,17 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
     });
   }
   __syncthreads();
-  flush_owned<T>(m, L, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
+  if constexpr (DET)
+    flush_det(m, L, acc, 1, dt.det, dt.ncells);
+  else
+    flush_owned<T>(m, L, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // g_bar_j(c) += coef * sum_n v_nj W(q_n + d_n - c), three meshes M apart; v
 // of slot a is read at slot src[a] (the order the cotangents were left in).
-template <typename T>
+// DET: the deterministic mode's output (dt, with dt.vmax = max |v|) instead
+// of out, zh and halo.
+template <typename T, bool DET>
 __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ d,
                                                           const T* __restrict__ v, T coef,
                                                           long long P, int lp, Grid<T> g,
@@ -783,8 +861,8 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
                                                           long long M,
                                                           const unsigned* __restrict__ src,
                                                           T* __restrict__ zh,
-                                                          T* __restrict__ halo) {
-  using A = WinAcc<T>;
+                                                          T* __restrict__ halo, DetOut dt) {
+  using A = PaintAcc<T, DET>;
   __shared__ typename A::Cell acc[3 * kWin];
   __shared__ double red[kThreads / 64];
   Item m;
@@ -802,15 +880,21 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
   }
   zero_window(acc, 3);
   double amax = 0.0;  // largest |coef v| of the item (the weights are at most 1)
+  if constexpr (!DET) {
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    if (!ok[k]) continue;
+    for (int k = 0; k < kPer; ++k) {
+      if (!ok[k]) continue;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) amax = fmax(amax, fabs(static_cast<double>(coef * vv[k][q])));
+      for (int q = 0; q < 3; ++q) amax = fmax(amax, fabs(static_cast<double>(coef * vv[k][q])));
+    }
   }
   wg_max_issue(amax, red);
   __syncthreads();
-  const typename A::Scale sc = A::scale_for(wg_max_finish(red));
+  typename A::Scale sc;
+  if constexpr (DET)
+    sc = FixAcc::scale_det(det_amax<T>(dt.vmax, coef), dt.lpc);
+  else
+    sc = A::scale_for(wg_max_finish(red));
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     if (!ok[k]) continue;
@@ -827,7 +911,10 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
     });
   }
   __syncthreads();
-  flush_owned<T>(m, L, acc, sc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
+  if constexpr (DET)
+    flush_det(m, L, acc, 3, dt.det, dt.ncells);
+  else
+    flush_owned<T>(m, L, acc, sc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
 }
 
 // Readout of g at d_n, kick p += kick F, drift d' = d_n + drift p; the new
@@ -1037,15 +1124,16 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
 }
 
 // Data-grid paint of the redshift-space positions (items of the data order).
-template <typename T>
+// DET: the deterministic mode's output (dt) instead of rho, zh and halo.
+template <typename T, bool DET>
 __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__ d,
                                                            const T* __restrict__ p, long long P,
                                                            int lp, pk::Rsd<T> rsd, Grid<T> gd,
                                                            Layout Ld, Items it,
                                                            T* __restrict__ rho,
                                                            T* __restrict__ zh,
-                                                           T* __restrict__ halo) {
-  using A = WinAcc<T>;
+                                                           T* __restrict__ halo, DetOut dt) {
+  using A = PaintAcc<T, DET>;
   __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, Ld, m)) return;
@@ -1061,7 +1149,11 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
     pk::load3(p, P, a, mom[k]);
   }
   zero_window(acc, 1);
-  const typename A::Scale sc = A::scale_for(1.0);  // weights are at most 1
+  typename A::Scale sc;  // weights are at most 1
+  if constexpr (DET)
+    sc = FixAcc::scale_det(1.0, dt.lpc);
+  else
+    sc = A::scale_for(1.0);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -1074,7 +1166,10 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
     });
   }
   __syncthreads();
-  flush_owned<T>(m, Ld, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
+  if constexpr (DET)
+    flush_det(m, Ld, acc, 1, dt.det, dt.ncells);
+  else
+    flush_owned<T>(m, Ld, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
 
 // Adjoint of the RSD + data paint (see pk::k_data_adjoint) over the data

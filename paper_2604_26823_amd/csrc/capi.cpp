@@ -80,6 +80,8 @@ void validate_problem(const ic_problem& p) {
     bad(IC_ERR_INVALID_ARG, "unknown loss_kind");
   if (p.loss_kind == IC_LOSS_POISSON && !(p.bias_alpha > 0 && p.bias_k > 0))
     bad(IC_ERR_INVALID_ARG, "bias_alpha and bias_k must be positive");
+  if (p.deterministic != 0 && p.deterministic != 1)
+    bad(IC_ERR_INVALID_ARG, "deterministic must be 0 or 1");
   if (p.lc_n < 0 || p.lc_n > IC_MAX_SNAPSHOTS) bad(IC_ERR_INVALID_ARG, "lc_n must be in [0, 4]");
   if (p.lc_n > 0) {
     if (p.lc_iterations < 1 || p.lc_iterations > 16)

@@ -149,6 +149,13 @@ class Engine final : public EngineBase {
     hstage_ = c.take<T>((size_t)std::max<long long>(3ll * mim_, mid_) * bk::kHaloXY);
     zh_ = c.take<T>(3 * M_ / kZHalo);
     zhd_ = c.take<T>(P_ / kZHalo);
+    // deterministic mode: the paints' integer accumulation fields (three mesh
+    // fields, or the data grid) and the device maximum their scale is for
+    det_ = p.deterministic != 0;
+    if (det_) {
+      det64_ = c.take<unsigned long long>(3 * std::max(M_, P_));
+      detvmax_ = c.take<double>(8);
+    }
     tmpd_ = c.take<T>(3 * P_);
     tmpp_ = c.take<T>(3 * P_);
     dsd_ = c.take<T>(3 * P_);
@@ -664,6 +671,33 @@ class Engine final : public EngineBase {
     IC_LAUNCHED();
   }
 
+  // ------------------------------------------------- deterministic mode
+  // The paints accumulate in 64-bit fixed point with one scale per paint and
+  // add their windows into det64_ with integer atomics, so a paint's result
+  // depends neither on the atomics' order nor on which particles share a
+  // work item; the fields are then converted and left complete (their z
+  // halo buffers zeroed, no x/y halo pass).
+  bk::DetOut det_out(const double* vmax, long long ncells) const {
+    return bk::DetOut{det64_, vmax, ncells, 3 * lp_};
+  }
+  void fill_det(long long n) {
+    fk::k_fill<unsigned long long><<<grid_for(n, kThreads), kThreads, 0, st_>>>(det64_, 0ull, n);
+    IC_LAUNCHED();
+  }
+  void det_to_field(const double* vmax, T coef, int nf, long long ncells, const bk::MPtrs<T>& out) {
+    bk::k_det_to_field<T><<<grid_for(ncells, bk::kThreads), bk::kThreads, 0, st_>>>(
+        det64_, nf, ncells, vmax, coef, 3 * lp_, out);
+    IC_LAUNCHED();
+  }
+  // *out = max |x_i| over n values.
+  void absmax(const T* x, long long n, double* out) {
+    const unsigned g = grid_for(n, fk::kRedThreads, kRedBlocks);
+    fk::k_absmax_parts<T><<<g, fk::kRedThreads, 0, st_>>>(x, n, part_);
+    IC_LAUNCHED();
+    fk::k_max_parts<<<1, fk::kRedThreads, 0, st_>>>(part_, g, out);
+    IC_LAUNCHED();
+  }
+
   // rho = CIC density of the state in order o (positions d, ids id), its
   // z halo left in zh (ncells / 8 values) for the consumer; every cell of
   // rho and zh is written here.  With gsrc the positions are read as
@@ -671,12 +705,26 @@ class Engine final : public EngineBase {
   void paint(const T* d, const Order& o, const unsigned* id, const pk::Grid<T>& g,
              const bk::Layout& L, T* rho, T* zh, long long ncells,
              const unsigned* gsrc = nullptr, T* dcopy = nullptr) {
+    const double bytes = P_ * ((gsrc ? 6.0 : 3.0) * sizeT() + (gsrc ? 8.0 : 4.0)) +
+                         2.0 * ncells * sizeT();
+    if (det_) {
+      fill_det(ncells);
+      {
+        auto sc = timer_.scope("cic_paint", bytes);
+        bk::k_paint_b<T, true><<<o.max_items + 8, bk::kThreads, 0, st_>>>(
+            d, gsrc, dcopy, P_, lp_, g, L, items(o, id), rho, zh, hstage_,
+            det_out(nullptr, ncells));
+        IC_LAUNCHED();
+      }
+      det_to_field(nullptr, T(1), 1, ncells, bk::MPtrs<T>{{rho}});
+      fill(zh, T(0), ncells / kZHalo);
+      return;
+    }
     zero_unowned(o, L, 1, bk::MPtrs<T>{{rho}}, zh);
     {
-      auto sc = timer_.scope("cic_paint", P_ * ((gsrc ? 6.0 : 3.0) * sizeT() + (gsrc ? 8.0 : 4.0)) +
-                                               2.0 * ncells * sizeT());
-      bk::k_paint_b<T><<<o.max_items + 8, bk::kThreads, 0, st_>>>(
-          d, gsrc, dcopy, P_, lp_, g, L, items(o, id), rho, zh, hstage_);
+      auto sc = timer_.scope("cic_paint", bytes);
+      bk::k_paint_b<T, false><<<o.max_items + 8, bk::kThreads, 0, st_>>>(
+          d, gsrc, dcopy, P_, lp_, g, L, items(o, id), rho, zh, hstage_, bk::DetOut{});
       IC_LAUNCHED();
     }
     halo_rows(o, L, 1, bk::MPtrs<T>{{rho}});
@@ -950,12 +998,25 @@ class Engine final : public EngineBase {
     build_order(data_order());
     scatter(data_order(), state_ptrs(fd, fp), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
             dest(S_));
+    if (det_) {
+      fill_det(P_);
+      {
+        auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0) + 2.0 * P_ * sizeT());
+        bk::k_data_paint_b<T, true><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
+            dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), rhod_, zhd_,
+            hstage_, det_out(nullptr, P_));
+        IC_LAUNCHED();
+      }
+      det_to_field(nullptr, T(1), 1, P_, bk::MPtrs<T>{{rhod_}});
+      fill(zhd_, T(0), P_ / kZHalo);
+      return;
+    }
     zero_unowned(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}}, zhd_);
     {
       auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0) + 2.0 * P_ * sizeT());
-      bk::k_data_paint_b<T><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
+      bk::k_data_paint_b<T, false><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
           dsd_, psd_, P_, lp_, rsd(), gdata(), Ld_, items(data_order(), dids_), rhod_, zhd_,
-          hstage_);
+          hstage_, bk::DetOut{});
       IC_LAUNCHED();
     }
     halo_rows(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}});  // z halo: in zhd_, read by the loss
@@ -1099,14 +1160,30 @@ class Engine final : public EngineBase {
       const int js = n < S_ ? snapshot_index(n) : -1;
       const double r_snap = js >= 0 ? co_.K2[n - 1] / co_.kick[n] : 0.0;
       if (js >= 0) inject(dest(n), js, dbar_, T(1), static_cast<T>(r_snap));
-      zero_unowned(mesh_order(n), Lm_, 3, bk::MPtrs<T>{{gbar_, gbar_ + M_, gbar_ + 2 * M_}}, zh_);
-      {
-        auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
-        bk::k_paint_vec_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
-            dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), zh_, hstage_);
-        IC_LAUNCHED();
+      const bk::MPtrs<T> gb{{gbar_, gbar_ + M_, gbar_ + 2 * M_}};
+      if (det_) {
+        absmax(pbar_, 3 * P_, detvmax_);  // the paint's scale: max |p_bar| over all slots
+        fill_det(3 * M_);
+        {
+          auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
+          bk::k_paint_vec_b<T, true><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+              dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), zh_, hstage_,
+              det_out(detvmax_, M_));
+          IC_LAUNCHED();
+        }
+        det_to_field(detvmax_, coef, 3, M_, gb);
+        fill(zh_, T(0), 3 * M_ / kZHalo);
+      } else {
+        zero_unowned(mesh_order(n), Lm_, 3, gb, zh_);
+        {
+          auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
+          bk::k_paint_vec_b<T, false><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+              dslot(n), pbar_, coef, P_, lp_, gmesh(), Lm_, it, gbar_, M_, dest(n), zh_, hstage_,
+              bk::DetOut{});
+          IC_LAUNCHED();
+        }
+        halo_rows(mesh_order(n), Lm_, 3, gb);
       }
-      halo_rows(mesh_order(n), Lm_, 3, bk::MPtrs<T>{{gbar_, gbar_ + M_, gbar_ + 2 * M_}});
       const long long zm = M_ / kZHalo;
       GIn ins[3] = {{gbar_, T(1), nullptr, T(0), zh_},
                     {gbar_ + M_, T(1), nullptr, T(0), zh_ + zm},
@@ -1254,6 +1331,9 @@ class Engine final : public EngineBase {
   T* hstage_ = nullptr;
   T* zh_ = nullptr;
   T* zhd_ = nullptr;
+  bool det_ = false;                       // deterministic mode
+  unsigned long long* det64_ = nullptr;    // its integer paint fields
+  double* detvmax_ = nullptr;              // its cotangent paint's max |p_bar|
   static_assert(bk::kB == kZHalo, "the z halo spacing is the block side");
   T *tmpd_, *tmpp_, *dsd_, *psd_, *dbar2_, *pbar2_;
   T *vbuf_, *tbuf_;

@@ -176,6 +176,41 @@ static __global__ __launch_bounds__(kRedThreads) void k_reduce_parts(const doubl
   }
 }
 
+// Largest |x| over n values: per-block maxima into part, then their
+// maximum into out (one block).  Maxima do not depend on the order.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_absmax_parts(const T* __restrict__ x,
+                                                              long long n,
+                                                              double* __restrict__ part) {
+  __shared__ double sh[kRedThreads / 64];
+  double m = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(static_cast<double>(x[i])));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRedThreads / 64; ++w) m = fmax(m, sh[w]);
+    part[blockIdx.x] = fmax(m, sh[0]);
+  }
+}
+
+static __global__ __launch_bounds__(kRedThreads) void k_max_parts(const double* __restrict__ part,
+                                                                  int nblocks,
+                                                                  double* __restrict__ out) {
+  __shared__ double sh[kRedThreads / 64];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) m = fmax(m, part[b]);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kRedThreads / 64; ++w) m = fmax(m, sh[w]);
+    *out = m;
+  }
+}
+
 // Partial sums of a . b (b may be null: sum of a) and of (a - shift)^2 with
 // shift read from device memory (may be null).
 template <typename T>

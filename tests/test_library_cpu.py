@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_defaults(lib):
-    assert lib.ic_abi_version() == 5
+    assert lib.ic_abi_version() == 6
     p = _lib.IcProblem()
     lib.ic_problem_defaults(ctypes.byref(p))
     assert p.s_th == 10.0 and p.rom_nbins == 100 and p.rom_kmin == 0.1
