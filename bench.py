@@ -24,11 +24,13 @@ for FP32 and FP64; the FP64 CPU oracle timed on the host cores on whole
 loss + gradient evaluations of the same problem at 32^3 and 128^3; and one
 timing of a 256^3 FP32 real FFT round trip through torch.fft (hipFFT/rocFFT)
 beside the same round trip through this library's passes, for comparison
-only.
+only; and the same whole-evaluation timing in the deterministic mode
+(fixed-point paints, bitwise repeatable results) at the state the timed loop
+ended in, beside the default mode's.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
                        [--no-fp64] [--no-cpu-baseline] [--no-fft-compare]
-                       [--profile-steps P] [--copy-mib N]
+                       [--no-det-compare] [--profile-steps P] [--copy-mib N]
 """
 import argparse
 import json
@@ -241,6 +243,18 @@ def eval_roofline(ctx, s, cfg, elem, n=10):
     return out
 
 
+def det_compare(cfg, prec, counts, s_start, s_end, elem, ev_default):
+    """Whole evaluations in the deterministic mode at s_end, beside the
+    default mode's at the same state."""
+    import torch
+    ctx, _, _, _ = setup(dict(cfg, deterministic=1), prec, counts, s_start)
+    out = eval_roofline(ctx, s_end, cfg, elem)
+    del ctx
+    torch.cuda.empty_cache()
+    out["slowdown_vs_default"] = round(out["ms_per_eval"] / ev_default["ms_per_eval"], 4)
+    return out
+
+
 def fft_compare(ctx):
     """One 256^3 FP32 real FFT round trip through torch.fft (hipFFT/rocFFT)
     and through this library's passes (median of 10 each, HIP events).
@@ -320,6 +334,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fft-compare", action="store_true")
+    ap.add_argument("--no-det-compare", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, one device copy of this many MiB (a known-size "
@@ -355,9 +370,15 @@ def main():
         log("bench: FFT round-trip comparison")
         fftc = fft_compare(ctx)
     ws_gb = ctx.ws_bytes / 1e9
+    s_end = s.clone()
     del ctx, s
     r32.pop("g")
     torch.cuda.empty_cache()
+    det = None
+    if not a.no_det_compare:
+        log("bench: FP32 deterministic-mode evaluations")
+        det = {"fp32": det_compare(cfg, "f32", counts, s_start, s_end, 4, ev32)}
+    del s_end
 
     r64 = ev64 = None
     if not a.no_fp64:
@@ -367,8 +388,13 @@ def main():
         r64.pop("g")
         ev64 = eval_roofline(ctx64, s64, cfg, 8)
         log("bench: FP64 %d evals in %.3f s" % (r64["evals"], r64["seconds"]))
+        s64_end = s64.clone()
         del ctx64, s64
         torch.cuda.empty_cache()
+        if det is not None:
+            log("bench: FP64 deterministic-mode evaluations")
+            det["fp64"] = det_compare(cfg, "f64", counts, s_start, s64_end, 8, ev64)
+        del s64_end
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -402,6 +428,7 @@ def main():
         "eval_roofline": {"fp32": ev32, "fp64": ev64},
         "kernels": table,
         "fft_compare": fftc,
+        "deterministic": det,
         "workspace_gb": round(ws_gb, 2),
         "cpu_baseline": cpu,
     }

@@ -49,10 +49,18 @@ SCOPES = {
 }
 
 
+# Paint kernels instantiated for the deterministic mode (second template
+# argument true).
+DET_PAINTS = ("k_paint_b", "k_paint_vec_b", "k_data_paint_b")
+
+
 def short_name(kernel):
-    """'void ic::pk::k_paint_vec_t<float>(...)' -> ('k_paint_vec_t<float>', 'k_paint_vec_t')."""
+    """'void ic::pk::k_paint_vec_t<float>(...)' -> ('k_paint_vec_t<float>', 'k_paint_vec_t');
+    the deterministic-mode paints ('k_paint_b<float, true>') get a '_det' suffix."""
     k = kernel.split("(")[0].replace("void ", "").strip()
     base = k.split("<")[0].split("::")[-1]
+    if base in DET_PAINTS and ", true>" in k:
+        base += "_det"
     targ = ""
     if "<float" in k:
         targ = "<float>"
