@@ -117,6 +117,8 @@ LEDGER = {
     "fft_r2c_z": (0, 2),       # real field in, half spectrum out (mesh chains)
     "fft_y": (0, 2),
     "fft_c2r_z": (0, 2),
+    "fft_r2c_zy": (0, 2),      # the z and y passes fused (FP32, 256^3 grids)
+    "fft_c2r_yz": (0, 2),
 }
 
 

@@ -777,26 +777,43 @@ class Engine final : public EngineBase {
     cx<T>* S0 = pool_;
     cx<T>* So[kMaxMul];
     for (int j = 0; j < m; ++j) So[j] = pool_ + (j + 1) * H;
-    {
-      auto sc = timer_.scope("fft_r2c_z", (b ? 2 : 1) * U + Hb);
-      fft_r2c_z<T>(f, a, alpha, b, beta, S0, zh);
-    }
-    {
-      auto sc = timer_.scope("fft_y", 2 * Hb);
-      fft_y<T>(f, S0, true);
-    }
+    r2c_zy(f, a, alpha, b, beta, S0, zh, U, Hb);
     {
       auto sc = timer_.scope("fft_x_scatter", (1 + m) * Hb);
       fft_x_scatter<T>(f, S0, So, specs, m);
     }
-    for (int j = 0; j < m; ++j) {
-      {
-        auto sc = timer_.scope("fft_y", 2 * Hb);
-        fft_y<T>(f, So[j], false);
-      }
-      auto sc = timer_.scope("fft_c2r_z", Hb + U);
-      fft_c2r_z<T>(f, So[j], outs[j], T(1), nullptr, T(0));
+    for (int j = 0; j < m; ++j) c2r_yz(f, So[j], outs[j], nullptr, T(0), U, Hb);
+  }
+
+  // The z and y passes of a chain: fused into one pass where the grid allows
+  // (the chains' spectra are those of real fields), else two.
+  void r2c_zy(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* S,
+              const T* zh, double U, double Hb) {
+    if (fft_zy_fused<T>(f.n)) {
+      auto sc = timer_.scope("fft_r2c_zy", (b ? 2 : 1) * U + Hb);
+      fft_r2c_zy<T>(f, a, alpha, b, beta, S, zh);
+      return;
     }
+    {
+      auto sc = timer_.scope("fft_r2c_z", (b ? 2 : 1) * U + Hb);
+      fft_r2c_z<T>(f, a, alpha, b, beta, S, zh);
+    }
+    auto sc = timer_.scope("fft_y", 2 * Hb);
+    fft_y<T>(f, S, true);
+  }
+  void c2r_yz(const FftArgs<T>& f, cx<T>* S, T* out, const T* aux, T beta_aux, double U,
+              double Hb) {
+    if (!aux && fft_zy_fused<T>(f.n)) {
+      auto sc = timer_.scope("fft_c2r_yz", Hb + U);
+      fft_c2r_yz<T>(f, S, out);
+      return;
+    }
+    {
+      auto sc = timer_.scope("fft_y", 2 * Hb);
+      fft_y<T>(f, S, false);
+    }
+    auto sc = timer_.scope("fft_c2r_z", Hb + (aux ? 2 : 1) * U);
+    fft_c2r_z<T>(f, S, out, T(1), aux, beta_aux);
   }
 
   struct GIn {
@@ -817,26 +834,14 @@ class Engine final : public EngineBase {
     const cx<T>* Si[kMaxMul];
     for (int j = 0; j < m; ++j) {
       cx<T>* Sj = pool_ + j * H;
-      {
-        auto sc = timer_.scope("fft_r2c_z", (ins[j].b ? 2 : 1) * U + Hb);
-        fft_r2c_z<T>(f, ins[j].a, ins[j].alpha, ins[j].b, ins[j].beta, Sj, ins[j].zh);
-      }
-      {
-        auto sc = timer_.scope("fft_y", 2 * Hb);
-        fft_y<T>(f, Sj, true);
-      }
+      r2c_zy(f, ins[j].a, ins[j].alpha, ins[j].b, ins[j].beta, Sj, ins[j].zh, U, Hb);
       Si[j] = Sj;
     }
     {
       auto sc = timer_.scope("fft_x_gather", (1 + m) * Hb);
       fft_x_gather<T>(f, Si, specs, m, pool_);
     }
-    {
-      auto sc = timer_.scope("fft_y", 2 * Hb);
-      fft_y<T>(f, pool_, false);
-    }
-    auto sc = timer_.scope("fft_c2r_z", Hb + (aux ? 2 : 1) * U);
-    fft_c2r_z<T>(f, pool_, out, T(1), aux, beta_aux);
+    c2r_yz(f, pool_, out, aux, beta_aux, U, Hb);
   }
 
   // -------------------------------------------------------------- forward

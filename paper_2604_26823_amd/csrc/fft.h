@@ -10,7 +10,8 @@
 // one kernel runs the forward x FFT, multiplies by m multipliers and runs m
 // inverse x FFTs (scatter), or the reverse for m inputs summed into one
 // output (gather).  Inverse passes are unnormalised; the 1/n^3 of the
-// inverse real DFT is folded into the multiplier scale.
+// inverse real DFT is folded into the multiplier scale.  For FP32 at n = 256
+// the z and y passes also run fused, one x plane per workgroup.
 #pragma once
 
 #include "common.h"
@@ -68,6 +69,21 @@ void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<
 // out = alpha * (unnormalised inverse rfft along z of in) + beta * aux (aux may be null).
 template <typename T>
 void fft_c2r_z(const FftArgs<T>& f, const cx<T>* in, T* out, T alpha, const T* aux, T beta);
+
+// Whether the fused z and y passes below serve grid side n at this precision.
+template <typename T>
+bool fft_zy_fused(int n);
+
+// fft_r2c_z then the forward fft_y in one pass (where fft_zy_fused).
+template <typename T>
+void fft_r2c_zy(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out,
+                const T* zh = nullptr);
+
+// The inverse fft_y then fft_c2r_z (alpha 1, no aux) in one pass (where
+// fft_zy_fused), for the spectrum of a real field: its kz = 0 and kz = n/2
+// columns must be Hermitian along y (their inverse along y real).
+template <typename T>
+void fft_c2r_yz(const FftArgs<T>& f, const cx<T>* in, T* out);
 
 // In-place complex FFT along y of the half spectrum (forward or inverse, unnormalised).
 template <typename T>

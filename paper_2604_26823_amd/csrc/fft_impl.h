@@ -432,6 +432,227 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
   fft_line<T, n, false>(lane, buf, lidx, tw, 2, load0, storeL);
 }
 
+// ------------------------------------------ fused z and y passes (FP32, n = 256)
+// One workgroup transforms a whole x plane along z and y, so the plane's half
+// spectrum crosses HBM once instead of three times.  The plane (256 rows y of
+// 129 values kz) does not fit in LDS, so two identities shrink it:
+//  * the columns kz = 0 and kz = n/2 are real along y (the z transform of a
+//    real row is real there), so they travel as one complex column
+//    c(y) = X(y, 0) + i X(y, n/2): 128 complex columns;
+//  * one radix-2 step of the length-256 y transform splits it into two
+//    length-128 transforms: the even outputs are the transform of
+//    u(y) + u(y + 128), the odd ones that of (u(y) - u(y + 128)) W^y.
+// A 128 x 128 LDS tile plus 16 values per thread in registers then hold the
+// plane.  Forward: z transforms of rows 0-127 (through the tile, into
+// registers), of rows 128-255 (into the tile); the radix-2 step (sums to the
+// tile, differences to registers); the 128 even-output column transforms,
+// then the odd ones; the packed column's outputs are separated last
+// (X0 = (C[k] + conj C[-k]) / 2, X_{n/2} = (C[k] - conj C[-k]) / 2i).  The
+// inverse mirrors it; its packed column needs the kz = 0 and n/2 columns to
+// be Hermitian along y, which holds for the spectrum of any real field and
+// for the k-space multipliers applied to one (even ones real, odd ones
+// imaginary, the derivative ones zero at the Nyquist index).
+template <typename T, int N>
+struct ZYCfg {
+  static constexpr bool ok = false;
+};
+template <>
+struct ZYCfg<float, 256> {
+  static constexpr bool ok = true;
+  static constexpr int n = 128;                  // z row (complex), tile rows and columns
+  static constexpr int TPL = Plan<n>::TPL;       // threads per row or column transform
+  static constexpr int THREADS = n * TPL;        // 1024
+  static constexpr int LS = n + n / 16 + 2;      // tile row stride, as the z pass
+  static constexpr int OWN = THREADS / n;        // thread t owns rows t / n + OWN j of column t % n
+  static constexpr int PER = n / OWN;            // 16 held values per thread
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
+    const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
+    cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int kp,
+    const T* __restrict__ zh) {
+  using C = ZYCfg<T, N>;
+  constexpr int n = C::n;
+  __shared__ cx<T> buf[n * C::LS];
+  __shared__ cx<T> tw[N];
+  __shared__ cx<T> pk[2 * n];  // the packed column's even and odd outputs
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
+  const int t = threadIdx.x;
+  const size_t x = blockIdx.x;
+  const int lane = t % C::TPL, l = t / C::TPL;  // z phase: lane of tile row l
+  const int c = t % n, r0 = t / n;              // column phase and held values
+  const T half = static_cast<T>(0.5);
+  cx<T> keep[C::PER];
+  cx<T>* lb = buf + l * C::LS;
+  for (int h = 0; h < 2; ++h) {
+    const size_t line = x * N + h * n + l;
+    const cx<T>* ain = reinterpret_cast<const cx<T>*>(a + line * N);
+    const cx<T>* bin = b ? reinterpret_cast<const cx<T>*>(b + line * N) : nullptr;
+    auto load0 = [&](int e) -> cx<T> {
+      cx<T> u = ain[e];
+      if (zh && (e & (kZHalo / 2 - 1)) == 0)
+        u.x += zh[(size_t)(2 * e / kZHalo) * N * N + line];
+      cx<T> v = cscale<T>(u, alpha);
+      if (bin) {
+        cx<T> w = bin[e];
+        v.x += beta * w.x;
+        v.y += beta * w.y;
+      }
+      return v;
+    };
+    auto lidx = [&](int e) { return l * C::LS + zl(e); };
+    auto storeL = [&](int e, cx<T> v) { lb[zl(e)] = v; };
+    fft_line<T, n, true>(lane, buf, lidx, tw, 2, load0, storeL);
+    __syncthreads();
+    // the real transform's split, in place, pair (k, n - k) by one thread:
+    // X[k] = E + W^k (-i D), E, D = (Z[k] +- conj Z[n - k]) / 2; X[0] and
+    // X[n] (both real) packed into slot 0
+    for (int k = lane; k <= n / 2; k += C::TPL) {
+      const cx<T> zk = lb[zl(k)];
+      if (k == 0) {
+        lb[zl(0)] = mkc<T>(zk.x + zk.y, zk.x - zk.y);
+        continue;
+      }
+      const cx<T> zm = lb[zl(n - k)];
+      auto split = [&](cx<T> p, cx<T> q, int j) {
+        const cx<T> qc = cconj<T>(q);
+        const cx<T> e = cscale<T>(cadd<T>(p, qc), half);
+        const cx<T> d = cscale<T>(csub<T>(p, qc), half);
+        return cadd<T>(e, cmul<T>(tw[j], mkc<T>(d.y, -d.x)));
+      };
+      lb[zl(k)] = split(zk, zm, k);
+      if (k != n / 2) lb[zl(n - k)] = split(zm, zk, n - k);
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+      for (int j = 0; j < C::PER; ++j) keep[j] = buf[(r0 + C::OWN * j) * C::LS + zl(c)];
+    }
+    // the second half's first tile store follows a barrier in fft_line
+  }
+  // radix-2 step along y: rows y (held) and y + n (tile)
+#pragma unroll
+  for (int j = 0; j < C::PER; ++j) {
+    const int y = r0 + C::OWN * j;
+    cx<T>* q = buf + y * C::LS + zl(c);
+    const cx<T> lo = keep[j], hi = *q;
+    *q = cadd<T>(lo, hi);
+    keep[j] = cmul<T>(csub<T>(lo, hi), tw[y]);
+  }
+  __syncthreads();
+  auto cidx = [&](int e) { return e * C::LS + zl(c); };
+  auto cload = [&](int e) { return buf[cidx(e)]; };
+  for (int par = 0; par < 2; ++par) {
+    if (par == 1) {
+      // the even transforms' tile reads preceded their final barrier
+#pragma unroll
+      for (int j = 0; j < C::PER; ++j) buf[(r0 + C::OWN * j) * C::LS + zl(c)] = keep[j];
+      __syncthreads();
+    }
+    auto storeC = [&](int e, cx<T> v) {
+      if (c == 0)
+        pk[par * n + e] = v;
+      else
+        out[(x * N + 2 * e + par) * kp + c] = v;
+    };
+    fft_line<T, n, true>(r0, buf, cidx, tw, 2, cload, storeC);
+  }
+  __syncthreads();
+  for (int i = t; i < 2 * n; i += C::THREADS) {
+    const int par = i / n, e = i % n;
+    const int em = par == 0 ? ((n - e) & (n - 1)) : (n - 1 - e);  // output -k
+    const cx<T> cc = pk[i], cm = cconj<T>(pk[par * n + em]);
+    const cx<T> s = cadd<T>(cc, cm), d = csub<T>(cc, cm);
+    cx<T>* o = out + (x * N + 2 * e + par) * kp;
+    o[0] = cscale<T>(s, half);
+    o[n] = mkc<T>(half * d.y, -half * d.x);
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_c2r_yz(
+    const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ twg, int kp) {
+  using C = ZYCfg<T, N>;
+  constexpr int n = C::n;
+  __shared__ cx<T> buf[n * C::LS];
+  __shared__ cx<T> tw[N];
+  load_table<T>(tw, twg, N);  // visible after the first stage's barrier, before any use
+  const int t = threadIdx.x;
+  const size_t x = blockIdx.x;
+  const int c = t % n, r0 = t / n;
+  // held values: PER - 1 in registers, the last in LDS (the register file
+  // is full)
+  __shared__ cx<T> spare[C::THREADS];
+  cx<T> keep[C::PER - 1];
+  auto held = [&](int j) -> cx<T>& { return j < C::PER - 1 ? keep[j] : spare[t]; };
+  auto cidx = [&](int e) { return e * C::LS + zl(c); };
+  auto cstore = [&](int e, cx<T> v) { buf[cidx(e)] = v; };
+  // inverse y transforms of the even and odd rows ky, the packed column
+  // read as X(ky, 0) + i X(ky, n/2)
+  for (int par = 0; par < 2; ++par) {
+    auto load0 = [&](int e) -> cx<T> {
+      const cx<T>* row = in + (x * N + 2 * e + par) * kp;
+      if (c != 0) return row[c];
+      const cx<T> u = row[0], v = row[n];
+      return mkc<T>(u.x - v.y, u.y + v.x);
+    };
+    fft_line<T, n, false>(r0, buf, cidx, tw, 2, load0, cstore);
+    __syncthreads();
+    if (par == 0) {
+#pragma unroll
+      for (int j = 0; j < C::PER; ++j) held(j) = buf[(r0 + C::OWN * j) * C::LS + zl(c)];
+    }
+    // the odd transforms' first tile store follows a barrier in fft_line
+  }
+  // radix-2 step: u(y) = E(y) + W^-y O(y), u(y + n) = E(y) - W^-y O(y)
+#pragma unroll
+  for (int j = 0; j < C::PER; ++j) {
+    const int y = r0 + C::OWN * j;
+    cx<T>* q = buf + y * C::LS + zl(c);
+    const cx<T> o = cmul<T>(*q, cconj<T>(tw[y]));
+    const cx<T> e = held(j);
+    *q = cadd<T>(e, o);
+    held(j) = csub<T>(e, o);
+  }
+  __syncthreads();
+  const int lane = t % C::TPL, l = t / C::TPL;
+  cx<T>* lb = buf + l * C::LS;
+  // the real inverse's merge Z[e] = S + i W^-e D, S, D = X[e] +- conj X[n - e]
+  auto merge = [&](cx<T> xk, cx<T> xc, int e) {
+    const cx<T> s = cadd<T>(xk, xc);
+    const cx<T> d = csub<T>(xk, xc);
+    const cx<T> wd = cmul<T>(cconj<T>(tw[e]), d);
+    return mkc<T>(s.x - wd.y, s.y + wd.x);
+  };
+  auto lidx = [&](int e) { return l * C::LS + zl(e); };
+  auto lload = [&](int e) { return lb[zl(e)]; };
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1) {
+      // the first half's tile reads preceded the final barrier of its transform
+#pragma unroll
+      for (int j = 0; j < C::PER; ++j) buf[(r0 + C::OWN * j) * C::LS + zl(c)] = held(j);
+      __syncthreads();
+    }
+    // merge in place, pair (k, n - k) by one thread; X[0] and X[n] (real)
+    // packed in slot 0
+    for (int k = lane; k <= n / 2; k += C::TPL) {
+      const cx<T> xk = lb[zl(k)];
+      if (k == 0) {
+        lb[zl(0)] = merge(mkc<T>(xk.x, 0), mkc<T>(xk.y, 0), 0);
+        continue;
+      }
+      const cx<T> xm = lb[zl(n - k)];
+      lb[zl(k)] = merge(xk, cconj<T>(xm), k);
+      if (k != n / 2) lb[zl(n - k)] = merge(xm, cconj<T>(xk), n - k);
+    }
+    __syncthreads();
+    cx<T>* dst = reinterpret_cast<cx<T>*>(out + (x * N + h * n + l) * N);
+    auto storeL = [&](int e, cx<T> v) { dst[e] = v; };
+    fft_line<T, n, false>(lane, buf, lidx, tw, 2, lload, storeL);
+  }
+}
+
 // ------------------------------------------------- strided C2C (y or x)
 // Line L of the batch starts at (L / group) * gstride + L % group and its
 // elements are estride apart; lines with L mod vmod >= vcnt are row padding
@@ -660,6 +881,39 @@ void fft_c2r_z(const FftArgs<T>& f, const cx<T>* in, T* out, T alpha, const T* a
         in, out, alpha, aux, beta, f.tw, nlines, f.kp);
   });
   IC_LAUNCHED();
+}
+
+template <typename T>
+bool fft_zy_fused(int n) {
+  return fftk::ZYCfg<T, 256>::ok && n == 256;
+}
+
+template <typename T>
+void fft_r2c_zy(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<T>* out,
+                const T* zh) {
+  if constexpr (fftk::ZYCfg<T, 256>::ok) {
+    if (f.n == 256) {
+      using C = fftk::ZYCfg<T, 256>;
+      fftk::k_r2c_zy<T, 256><<<f.n, C::THREADS, 0, f.stream>>>(a, alpha, b, beta, out, f.tw,
+                                                               f.kp, zh);
+      IC_LAUNCHED();
+      return;
+    }
+  }
+  throw ApiError(-2, "fused z and y passes: FP32 at n = 256 only");
+}
+
+template <typename T>
+void fft_c2r_yz(const FftArgs<T>& f, const cx<T>* in, T* out) {
+  if constexpr (fftk::ZYCfg<T, 256>::ok) {
+    if (f.n == 256) {
+      using C = fftk::ZYCfg<T, 256>;
+      fftk::k_c2r_yz<T, 256><<<f.n, C::THREADS, 0, f.stream>>>(in, out, f.tw, f.kp);
+      IC_LAUNCHED();
+      return;
+    }
+  }
+  throw ApiError(-2, "fused y and z passes: FP32 at n = 256 only");
 }
 
 template <typename T>

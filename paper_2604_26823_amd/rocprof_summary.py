@@ -39,6 +39,8 @@ SCOPES = {
     "k_keys": "sort_keys",
     "k_r2c_z": "fft_r2c_z",
     "k_c2r_z": "fft_c2r_z",
+    "k_r2c_zy": "fft_r2c_zy",
+    "k_c2r_yz": "fft_c2r_yz",
     "k_strided": "fft_y",
     "k_x_scatter": "fft_x_scatter",
     "k_x_gather": "fft_x_gather",

@@ -50,9 +50,12 @@ def test_irfft_matches_oracle(prec, n):
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("kind", [("grad", 0), ("grad", 2), ("hess", (0, 1)), ("hess", (2, 2)),
                                   ("white", None)])
-def test_multiplier_operators(prec, kind):
+@pytest.mark.parametrize("n", [32, 256])
+def test_multiplier_operators(prec, kind, n):
+    """Op_m[x] = irfft(m rfft(x)) through one scatter chain; at n = 256 the
+    FP32 chain runs the fused z+y passes (the packed kz = 0 / n/2 column,
+    the hand radix-2 step along y)."""
     require_gpu()
-    n = 32
     cfg = small(n)
     ctx = context(cfg, prec)
     mdl = model(cfg)
