@@ -469,13 +469,42 @@ __device__ __forceinline__ bool item_of(const Items& it, const Layout& L, Item& 
   return true;
 }
 
-// Slot k of this thread in the item: slot index, Lagrangian lattice index.
-__device__ __forceinline__ bool item_slot(const Item& m, const Items& it, int k, int lp,
-                                          long long& a, int idx[3]) {
-  a = static_cast<long long>(m.s0) + threadIdx.x + k * kThreads;
-  if (a >= m.s1) return false;
-  pk::lattice(static_cast<long long>(it.ids[a]), lp, idx);
-  return true;
+// Slots a[k] = s0 + threadIdx.x + k kThreads of this thread in the item and
+// whether they hold a particle; slots past the item's end are clamped to its
+// first slot (an item is never empty).  The kernels issue the loads of all
+// kPer particles from these slots in one branch-free run and wait once:
+// behind a branch per particle, the in-order memory counter made every
+// particle's loads wait for all of the previous particle's.
+__device__ __forceinline__ void item_slots(const Item& m, long long (&a)[kPer],
+                                           bool (&ok)[kPer]) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const long long s = static_cast<long long>(m.s0) + threadIdx.x + k * kThreads;
+    ok[k] = s < static_cast<long long>(m.s1);
+    a[k] = ok[k] ? s : static_cast<long long>(m.s0);
+  }
+}
+
+// u[k] = map[a[k]] (particle ids, slot maps).
+__device__ __forceinline__ void load_u32(const unsigned* __restrict__ map,
+                                         const long long (&a)[kPer], unsigned (&u)[kPer]) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) u[k] = map[a[k]];
+}
+
+// v[k] = the three fields of f (P apart) at slot s[k].
+template <typename T, typename S>
+__device__ __forceinline__ void load3_at(const T* __restrict__ f, long long P,
+                                         const S (&s)[kPer], T (&v)[kPer][3]) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) pk::load3(f, P, static_cast<long long>(s[k]), v[k]);
+}
+
+// Lagrangian lattice indices of the particle ids.
+__device__ __forceinline__ void lattice_all(const unsigned (&id)[kPer], int lp,
+                                            int (&idx)[kPer][3]) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) pk::lattice(static_cast<long long>(id[k]), lp, idx[k]);
 }
 
 template <typename T>
@@ -812,22 +841,31 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
   __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, L, m)) return;
+  long long a[kPer];
   bool ok[kPer];
+  unsigned id[kPer];
   int idx[kPer][3];
   T dsp[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
-    long long a;
-    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, gsrc ? static_cast<long long>(gsrc[a]) : a, dsp[k]);
-    if (dcopy) {
-      dcopy[a] = dsp[k][0];
-      dcopy[P + a] = dsp[k][1];
-      dcopy[2 * P + a] = dsp[k][2];
-    }
+  item_slots(m, a, ok);  // loads in flight while the window is cleared
+  load_u32(it.ids, a, id);
+  if (gsrc) {
+    unsigned sa[kPer];
+    load_u32(gsrc, a, sa);
+    load3_at(d, P, sa, dsp);
+  } else {
+    load3_at(d, P, a, dsp);
   }
   zero_window(acc, 1);
+  if (dcopy) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (!ok[k]) continue;
+      dcopy[a[k]] = dsp[k][0];
+      dcopy[P + a[k]] = dsp[k][1];
+      dcopy[2 * P + a[k]] = dsp[k][2];
+    }
+  }
+  lattice_all(id, lp, idx);
   typename A::Scale sc;  // weights are at most 1
   if constexpr (DET)
     sc = FixAcc::scale_det(1.0, dt.lpc);
@@ -867,18 +905,18 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
   __shared__ double red[kThreads / 64];
   Item m;
   if (!item_of<false>(it, L, m)) return;
+  long long a[kPer];
   bool ok[kPer];
+  unsigned id[kPer], sa[kPer];
   int idx[kPer][3];
   T dsp[kPer][3], vv[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
-    long long a;
-    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a, dsp[k]);
-    pk::load3(v, P, static_cast<long long>(src[a]), vv[k]);
-  }
+  item_slots(m, a, ok);  // loads in flight while the window is cleared
+  load_u32(it.ids, a, id);
+  load_u32(src, a, sa);
+  load3_at(d, P, a, dsp);
+  load3_at(v, P, sa, vv);
   zero_window(acc, 3);
+  lattice_all(id, lp, idx);
   double amax = 0.0;  // largest |coef v| of the item (the weights are at most 1)
   if constexpr (!DET) {
 #pragma unroll
@@ -933,17 +971,22 @@ __global__ __launch_bounds__(kThreads) void k_step_b(
   if (!item_of<true>(it, L, m)) return;
   long long a[kPer];
   bool ok[kPer];
-  unsigned b[kPer];
+  unsigned b[kPer], id[kPer];
   int idx[kPer][3];
   T dsp[kPer][3], mom[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
-    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(p, P, pinv ? static_cast<long long>(pinv[a[k]]) : a[k], mom[k]);
+  item_slots(m, a, ok);  // particle loads in flight while the window loads
+  load_u32(it.ids, a, id);
+  if (pinv) {
+    unsigned sa[kPer];
+    load_u32(pinv, a, sa);
+    load3_at(d, P, a, dsp);
+    load3_at(p, P, sa, mom);
+  } else {
+    load3_at(d, P, a, dsp);
+    load3_at(p, P, a, mom);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
+  lattice_all(id, lp, idx);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -1011,17 +1054,16 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
   long long a[kPer];
   int idx[kPer][3];
   bool ok[kPer];
+  unsigned id[kPer], sa[kPer];
   T dsp[kPer][3], pb[kPer][3], db[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a[k], dsp[k]);
-    const long long sa = static_cast<long long>(src[a[k]]);
-    pk::load3(pbar, P, sa, pb[k]);
-    pk::load3(dbar, P, sa, db[k]);
-  }
+  item_slots(m, a, ok);  // particle loads in flight while the window loads
+  load_u32(it.ids, a, id);
+  load_u32(src, a, sa);
+  load3_at(d, P, a, dsp);
+  load3_at(pbar, P, sa, pb);
+  load3_at(dbar, P, sa, db);
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M, rho_bar}}, 4, lds);
+  lattice_all(id, lp, idx);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -1061,17 +1103,22 @@ __global__ __launch_bounds__(kThreads) void k_final_b(
   if (!item_of<true>(it, L, m)) return;
   long long a[kPer];
   bool ok[kPer];
-  unsigned b[kPer];
+  unsigned b[kPer], id[kPer];
   int idx[kPer][3];
   T dsp[kPer][3], mom[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
-    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(p, P, pinv ? static_cast<long long>(pinv[a[k]]) : a[k], mom[k]);
+  item_slots(m, a, ok);  // particle loads in flight while the window loads
+  load_u32(it.ids, a, id);
+  if (pinv) {
+    unsigned sa[kPer];
+    load_u32(pinv, a, sa);
+    load3_at(d, P, a, dsp);
+    load3_at(p, P, sa, mom);
+  } else {
+    load3_at(d, P, a, dsp);
+    load3_at(p, P, a, mom);
   }
   load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
+  lattice_all(id, lp, idx);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -1137,18 +1184,17 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
   __shared__ typename A::Cell acc[kWin];
   Item m;
   if (!item_of<false>(it, Ld, m)) return;
+  long long a[kPer];
   bool ok[kPer];
+  unsigned id[kPer];
   int idx[kPer][3];
   T dsp[kPer][3], mom[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // loads in flight while the window is cleared
-    long long a;
-    ok[k] = item_slot(m, it, k, lp, a, idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a, dsp[k]);
-    pk::load3(p, P, a, mom[k]);
-  }
+  item_slots(m, a, ok);  // loads in flight while the window is cleared
+  load_u32(it.ids, a, id);
+  load3_at(d, P, a, dsp);
+  load3_at(p, P, a, mom);
   zero_window(acc, 1);
+  lattice_all(id, lp, idx);
   typename A::Scale sc;  // weights are at most 1
   if constexpr (DET)
     sc = FixAcc::scale_det(1.0, dt.lpc);
@@ -1184,16 +1230,15 @@ __global__ __launch_bounds__(kThreads) void k_data_adjoint_b(
   if (!item_of<true>(it, Ld, m)) return;
   long long a[kPer];
   bool ok[kPer];
+  unsigned id[kPer];
   int idx[kPer][3];
   T dsp[kPer][3], mom[kPer][3];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {  // particle loads in flight while the window loads
-    ok[k] = item_slot(m, it, k, lp, a[k], idx[k]);
-    if (!ok[k]) continue;
-    pk::load3(d, P, a[k], dsp[k]);
-    pk::load3(p, P, a[k], mom[k]);
-  }
+  item_slots(m, a, ok);  // particle loads in flight while the window loads
+  load_u32(it.ids, a, id);
+  load3_at(d, P, a, dsp);
+  load3_at(p, P, a, mom);
   load_window<T>(m.o, Ld, Ptrs<T>{{rho_bar}}, 1, lds);
+  lattice_all(id, lp, idx);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
