@@ -13,6 +13,8 @@
 // consecutive threads because its lines are contiguous.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 
 namespace ic {
@@ -334,10 +336,34 @@ __device__ __forceinline__ void load_table(cx<T>* dst, const cx<T>* __restrict__
 }
 
 // ------------------------------------------------------------ z pass R2C
+// Element e of z row `line` (its complex pair 2e, 2e + 1) of
+// alpha (a + zh) + beta b, without a branch: ZH and B are compile-time, and
+// the z-halo value (added to the cells z = 0 mod 8) is loaded for every e and
+// selected, so the loads of a transform's first stage are all issued before
+// its first wait (a branch per element made each load wait for the previous).
+template <typename T, int N, bool ZH, bool B>
+__device__ __forceinline__ cx<T> r2c_elem(const cx<T>* __restrict__ ain,
+                                          const cx<T>* __restrict__ bin,
+                                          const T* __restrict__ zh, size_t line, int e,
+                                          T alpha, T beta) {
+  cx<T> u = ain[e];
+  if constexpr (ZH) {
+    const T z = zh[(size_t)(2 * e / kZHalo) * N * N + line];
+    u.x += (e & (kZHalo / 2 - 1)) == 0 ? z : static_cast<T>(0);
+  }
+  cx<T> v = cscale<T>(u, alpha);
+  if constexpr (B) {
+    const cx<T> w = bin[e];
+    v.x += beta * w.x;
+    v.y += beta * w.y;
+  }
+  return v;
+}
+
 // zh (nullable): a paint's z halo, one value per eight cells along z, added
 // to the cells z = 0 mod 8 of a (the value of cell z of line L = x N + y is
 // zh[(z / 8) N^2 + L]).
-template <typename T, int N>
+template <typename T, int N, bool ZH, bool B>
 __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
     const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
     cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int nlines, int kp,
@@ -351,20 +377,12 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_r2c_z(
   const int l = threadIdx.x / C::TPL;
   const int line = blockIdx.x * C::LINES + l;
   const bool valid = line < nlines;
-  const cx<T>* ain = reinterpret_cast<const cx<T>*>(a + (size_t)line * N);
-  const cx<T>* bin = b ? reinterpret_cast<const cx<T>*>(b + (size_t)line * N) : nullptr;
+  // past the last line: row 0 is transformed and not stored
+  const size_t lrow = valid ? static_cast<size_t>(line) : 0;
+  const cx<T>* ain = reinterpret_cast<const cx<T>*>(a + lrow * N);
+  const cx<T>* bin = B ? reinterpret_cast<const cx<T>*>(b + lrow * N) : nullptr;
   auto load0 = [&](int e) -> cx<T> {
-    if (!valid) return mkc<T>(0, 0);
-    cx<T> u = ain[e];
-    if (zh && (e & (kZHalo / 2 - 1)) == 0)
-      u.x += zh[(size_t)(2 * e / kZHalo) * N * N + line];
-    cx<T> v = cscale<T>(u, alpha);
-    if (bin) {
-      cx<T> w = bin[e];
-      v.x += beta * w.x;
-      v.y += beta * w.y;
-    }
-    return v;
+    return r2c_elem<T, N, ZH, B>(ain, bin, zh, lrow, e, alpha, beta);
   };
   cx<T>* lb = buf + l * C::LS;
   auto lidx = [&](int e) { return l * C::LS + zl(e); };
@@ -467,7 +485,7 @@ struct ZYCfg<float, 256> {
   static constexpr int PER = n / OWN;            // 16 held values per thread
 };
 
-template <typename T, int N>
+template <typename T, int N, bool ZH, bool B>
 __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
     const T* __restrict__ a, T alpha, const T* __restrict__ b, T beta,
     cx<T>* __restrict__ out, const cx<T>* __restrict__ twg, int kp,
@@ -483,19 +501,39 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
   const int lane = t % C::TPL, l = t / C::TPL;  // z phase: lane of tile row l
   const int c = t % n, r0 = t / n;              // column phase and held values
   const T half = static_cast<T>(0.5);
-  cx<T> keep[C::PER];
+  // held values: PER - SPARE in registers, the rest in LDS (the register
+  // file is full)
+  constexpr int SPARE = 1;
+  __shared__ cx<T> spare[SPARE * C::THREADS];
+  cx<T> keep[C::PER - SPARE];
+  auto held = [&](int j) -> cx<T>& {
+    return j < C::PER - SPARE ? keep[j] : spare[(j - (C::PER - SPARE)) * C::THREADS + t];
+  };
   cx<T>* lb = buf + l * C::LS;
+  // the half's z-halo values, staged in the tile as [z / 8][row] by coalesced
+  // loads (a row's 32 values lie a plane apart in zh)
+  constexpr int NZ = N / kZHalo;
+  const T* zt = reinterpret_cast<const T*>(buf);
   for (int h = 0; h < 2; ++h) {
     const size_t line = x * N + h * n + l;
     const cx<T>* ain = reinterpret_cast<const cx<T>*>(a + line * N);
-    const cx<T>* bin = b ? reinterpret_cast<const cx<T>*>(b + line * N) : nullptr;
-    auto load0 = [&](int e) -> cx<T> {
+    const cx<T>* bin = B ? reinterpret_cast<const cx<T>*>(b + line * N) : nullptr;
+    if constexpr (ZH) {
+      if (h == 1) __syncthreads();  // the first half's held values are read
+      T* zw = reinterpret_cast<T*>(buf);
+      for (int i = t; i < NZ * n; i += C::THREADS)
+        zw[i] = zh[(size_t)(i / n) * N * N + x * N + h * n + i % n];
+      __syncthreads();
+    }
+    auto load0 = [&](int e) -> cx<T> {  // no branch: all loads out before the first wait
       cx<T> u = ain[e];
-      if (zh && (e & (kZHalo / 2 - 1)) == 0)
-        u.x += zh[(size_t)(2 * e / kZHalo) * N * N + line];
+      if constexpr (ZH) {
+        const T z = zt[(2 * e / kZHalo) * n + l];
+        u.x += (e & (kZHalo / 2 - 1)) == 0 ? z : static_cast<T>(0);
+      }
       cx<T> v = cscale<T>(u, alpha);
-      if (bin) {
-        cx<T> w = bin[e];
+      if constexpr (B) {
+        const cx<T> w = bin[e];
         v.x += beta * w.x;
         v.y += beta * w.y;
       }
@@ -527,7 +565,7 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
     __syncthreads();
     if (h == 0) {
 #pragma unroll
-      for (int j = 0; j < C::PER; ++j) keep[j] = buf[(r0 + C::OWN * j) * C::LS + zl(c)];
+      for (int j = 0; j < C::PER; ++j) held(j) = buf[(r0 + C::OWN * j) * C::LS + zl(c)];
     }
     // the second half's first tile store follows a barrier in fft_line
   }
@@ -536,9 +574,9 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
   for (int j = 0; j < C::PER; ++j) {
     const int y = r0 + C::OWN * j;
     cx<T>* q = buf + y * C::LS + zl(c);
-    const cx<T> lo = keep[j], hi = *q;
+    const cx<T> lo = held(j), hi = *q;
     *q = cadd<T>(lo, hi);
-    keep[j] = cmul<T>(csub<T>(lo, hi), tw[y]);
+    held(j) = cmul<T>(csub<T>(lo, hi), tw[y]);
   }
   __syncthreads();
   auto cidx = [&](int e) { return e * C::LS + zl(c); };
@@ -547,7 +585,7 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
     if (par == 1) {
       // the even transforms' tile reads preceded their final barrier
 #pragma unroll
-      for (int j = 0; j < C::PER; ++j) buf[(r0 + C::OWN * j) * C::LS + zl(c)] = keep[j];
+      for (int j = 0; j < C::PER; ++j) buf[(r0 + C::OWN * j) * C::LS + zl(c)] = held(j);
       __syncthreads();
     }
     auto storeC = [&](int e, cx<T> v) {
@@ -591,11 +629,10 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_c2r_yz(
   // inverse y transforms of the even and odd rows ky, the packed column
   // read as X(ky, 0) + i X(ky, n/2)
   for (int par = 0; par < 2; ++par) {
-    auto load0 = [&](int e) -> cx<T> {
+    auto load0 = [&](int e) -> cx<T> {  // both loads for every column: no branch
       const cx<T>* row = in + (x * N + 2 * e + par) * kp;
-      if (c != 0) return row[c];
-      const cx<T> u = row[0], v = row[n];
-      return mkc<T>(u.x - v.y, u.y + v.x);
+      const cx<T> u = row[c], v = row[n];
+      return c != 0 ? u : mkc<T>(u.x - v.y, u.y + v.x);
     };
     fft_line<T, n, false>(r0, buf, cidx, tw, 2, load0, cstore);
     __syncthreads();
@@ -828,6 +865,24 @@ __global__ void k_spec_copy(const cx<T>* __restrict__ src, cx<T>* __restrict__ d
 }
 
 // ------------------------------------------------------------ dispatch
+// f(ZH, B) with the two flags as compile-time constants.
+template <class F>
+void with_flags(bool zh, bool b, F&& f) {
+  using Y = std::true_type;
+  using No = std::false_type;
+  if (zh) {
+    if (b)
+      f(Y{}, Y{});
+    else
+      f(Y{}, No{});
+  } else {
+    if (b)
+      f(No{}, Y{});
+    else
+      f(No{}, No{});
+  }
+}
+
 template <typename T, class F>
 void dispatch_n(int n, F&& f) {
   switch (n) {
@@ -865,8 +920,11 @@ void fft_r2c_z(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx<
     constexpr int N = decltype(NC)::value;
     using C = fftk::ZCfg<T, N>;
     const int nlines = f.n * f.n;
-    fftk::k_r2c_z<T, N><<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(
-        a, alpha, b, beta, out, f.tw, nlines, f.kp, zh);
+    fftk::with_flags(zh != nullptr, b != nullptr, [&](auto ZH, auto B) {
+      fftk::k_r2c_z<T, N, ZH.value, B.value>
+          <<<blocks_for(nlines, C::LINES), C::THREADS, 0, f.stream>>>(a, alpha, b, beta, out,
+                                                                      f.tw, nlines, f.kp, zh);
+    });
   });
   IC_LAUNCHED();
 }
@@ -894,8 +952,10 @@ void fft_r2c_zy(const FftArgs<T>& f, const T* a, T alpha, const T* b, T beta, cx
   if constexpr (fftk::ZYCfg<T, 256>::ok) {
     if (f.n == 256) {
       using C = fftk::ZYCfg<T, 256>;
-      fftk::k_r2c_zy<T, 256><<<f.n, C::THREADS, 0, f.stream>>>(a, alpha, b, beta, out, f.tw,
-                                                               f.kp, zh);
+      fftk::with_flags(zh != nullptr, b != nullptr, [&](auto ZH, auto B) {
+        fftk::k_r2c_zy<T, 256, ZH.value, B.value>
+            <<<f.n, C::THREADS, 0, f.stream>>>(a, alpha, b, beta, out, f.tw, f.kp, zh);
+      });
       IC_LAUNCHED();
       return;
     }
