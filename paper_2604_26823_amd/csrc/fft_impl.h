@@ -418,9 +418,18 @@ __global__ __launch_bounds__((ZCfg<T, N>::THREADS)) void k_c2r_z(
   const int line = blockIdx.x * C::LINES + l;
   const bool valid = line < nlines;
   cx<T>* lb = buf + l * C::LS;
-  const cx<T>* src = in + (size_t)line * kp;
-  for (int k = lane; k <= n; k += C::TPL) {
-    cx<T> v = valid ? src[k] : mkc<T>(0, 0);
+  // the row's n + 1 values, all loads out before the first wait (no branch:
+  // indices clamped, lines past the end read line 0 and store zeros)
+  const cx<T>* src = in + (valid ? (size_t)line : 0) * kp;
+  constexpr int KS = n / C::TPL + 1;
+  cx<T> rv[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) rv[j] = src[min(lane + j * C::TPL, n)];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    const int k = lane + j * C::TPL;
+    if (k > n) continue;
+    cx<T> v = valid ? rv[j] : mkc<T>(0, 0);
     if (k == 0 || k == n) v.y = 0;  // the real transform ignores these imaginary parts
     lb[zl(k)] = v;
   }
@@ -513,6 +522,7 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
   // the half's z-halo values, staged in the tile as [z / 8][row] by coalesced
   // loads (a row's 32 values lie a plane apart in zh)
   constexpr int NZ = N / kZHalo;
+  static_assert(NZ * C::n % C::THREADS == 0, "z-halo staging: whole rounds");
   const T* zt = reinterpret_cast<const T*>(buf);
   for (int h = 0; h < 2; ++h) {
     const size_t line = x * N + h * n + l;
@@ -521,8 +531,15 @@ __global__ __launch_bounds__((ZYCfg<T, N>::THREADS)) void k_r2c_zy(
     if constexpr (ZH) {
       if (h == 1) __syncthreads();  // the first half's held values are read
       T* zw = reinterpret_cast<T*>(buf);
-      for (int i = t; i < NZ * n; i += C::THREADS)
-        zw[i] = zh[(size_t)(i / n) * N * N + x * N + h * n + i % n];
+      constexpr int QZ = NZ * n / C::THREADS;
+      T zv[QZ];
+#pragma unroll
+      for (int q = 0; q < QZ; ++q) {
+        const int i = t + q * C::THREADS;
+        zv[q] = zh[(size_t)(i / n) * N * N + x * N + h * n + i % n];
+      }
+#pragma unroll
+      for (int q = 0; q < QZ; ++q) zw[t + q * C::THREADS] = zv[q];
       __syncthreads();
     }
     auto load0 = [&](int e) -> cx<T> {  // no branch: all loads out before the first wait
