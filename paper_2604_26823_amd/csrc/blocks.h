@@ -791,17 +791,47 @@ __global__ __launch_bounds__(kThreads) void k_halo_rows(const T* __restrict__ ha
                           static_cast<unsigned>(q >> L.lnb) & bm, static_cast<unsigned>(q) & bm};
   const int l[3] = {yface ? lane >> 3 : 0, yface ? 0 : lane >> 3, lane & 7};
   if (yface && l[0] == 0) return;
-  T sum[NF];
+  // The six neighbour classes a = 2..7 = (ax ay az) as bits 2 1 0 with ax or
+  // ay set: whether the lane's cell takes that class's halo, the
+  // neighbour's item range and the halo entry.  The item ranges of all
+  // classes, then the first items' values, are loaded in one branch-free
+  // run each (clamped to item 0 and selected where unused); further items
+  // (blocks with several) follow in a loop.
+  constexpr int kA = 6;
+  bool use[kA];
+  int h[kA];
+  unsigned i0[kA], i1[kA];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) sum[f] = T(0);
-  for (int a = 2; a < 8; ++a) {  // a = (ax ay az) as bits 2 1 0, ax or ay set
+  for (int q = 0; q < kA; ++q) {
+    const int a = q + 2;
     const int ax = (a >> 2) & 1, ay = (a >> 1) & 1, az = a & 1;
-    if ((ax && l[0]) || (ay && l[1]) || (az && l[2])) continue;
+    use[q] = !((ax && l[0]) || (ay && l[1]) || (az && l[2]));
     const unsigned nbk = (((bb[0] - ax) & bm) << (2 * L.lnb)) | (((bb[1] - ay) & bm) << L.lnb) |
                          ((bb[2] - az) & bm);
-    const int h = halo_xy_index(ax ? kB : l[0], ay ? kB : l[1], az ? kB : l[2]);
-    for (unsigned i = istart[nbk]; i < istart[nbk + 1]; ++i) {
-      const T* hs = halo + static_cast<size_t>(i) * NF * kHaloXY + h;
+    h[q] = halo_xy_index(ax ? kB : l[0], ay ? kB : l[1], az ? kB : l[2]);
+    i0[q] = istart[nbk];
+    i1[q] = istart[nbk + 1];
+  }
+  T v[kA][NF];
+#pragma unroll
+  for (int q = 0; q < kA; ++q) {
+    use[q] = use[q] && i0[q] < i1[q];
+    const T* hs = halo + static_cast<size_t>(use[q] ? i0[q] : 0u) * NF * kHaloXY + h[q];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[q][f] = hs[f * kHaloXY];
+  }
+  T sum[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    sum[f] = T(0);
+#pragma unroll
+    for (int q = 0; q < kA; ++q) sum[f] += use[q] ? v[q][f] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < kA; ++q) {
+    if (!use[q]) continue;
+    for (unsigned i = i0[q] + 1; i < i1[q]; ++i) {
+      const T* hs = halo + static_cast<size_t>(i) * NF * kHaloXY + h[q];
 #pragma unroll
       for (int f = 0; f < NF; ++f) sum[f] += hs[f * kHaloXY];
     }
