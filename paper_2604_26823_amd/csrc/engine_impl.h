@@ -52,7 +52,7 @@ template <typename T>
 class Engine final : public EngineBase {
  public:
   static constexpr unsigned kThreads = 256;
-  static constexpr unsigned kRedBlocks = 1024;
+  static constexpr unsigned kRedBlocks = 4096;
 
   Engine(const ic_problem& p, char* ws, size_t ws_bytes, hipStream_t stream)
       : prob_(p), st_(stream) {

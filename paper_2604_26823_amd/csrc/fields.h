@@ -105,52 +105,71 @@ __global__ __launch_bounds__(kRedThreads) void k_loss(
     const T* __restrict__ zh, int lg) {
   __shared__ double sh[kRedThreads / 64];
   double chi = 0, ss = 0, cnt = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    // the data paint's z halo (layout [z / 8][x][y], grid side 2^lg)
-    // completes the cells z = 0 mod 8
-    const T rh = rho[i] + ((zh && (i & 7) == 0)
-                               ? zh[((i & ((1ll << lg) - 1)) >> 3 << (2 * lg)) | (i >> lg)]
-                               : T(0));
-    const T delta = rh - T(1);
-    T sd = T(0);
-    if (delta_out) delta_out[i] = delta;
-    if (R) {
-      const T r = R[i];
-      T lam, dlam = T(0);
-      if (o.poisson) {
-        // u = 1 + delta is the painted density itself: taken from rho, not
-        // from 1 + (rho - 1), whose cancellation would leave nearly empty
-        // cells (u near the floor) with FP32 rounding of order 1e-7 / u
-        const T u = rh > T(kUFloor) ? rh : T(kUFloor);
-        const T sig = T(1) / (T(1) + exp(-o.k * (delta - o.delta_th)));
-        const T ua = pow(u, o.alpha);
-        lam = o.nbar * r * ua * sig;
-        const T du = rh > T(kUFloor) ? o.alpha * ua / u : T(0);
-        dlam = o.nbar * r * (du * sig + ua * o.k * sig * (T(1) - sig));
-      } else {
-        lam = o.nbar * r * (T(1) + o.bias * delta);
-      }
-      if (lambda_out) lambda_out[i] = lam;
-      if (counts && r >= o.r_min) {
-        const int nc = counts[i];
-        if (o.poisson) {
-          const double l = static_cast<double>(lam), nn = static_cast<double>(nc);
-          chi += 2.0 * (l - nn * log(l) + lgamma(nn + 1.0));
-          sd = (T(1) - static_cast<T>(nc) / lam) * dlam;
-        } else {
-          const T var = o.nbar * r;
-          const double res = static_cast<double>(nc) - static_cast<double>(lam);
-          chi += res * res / static_cast<double>(var);
-          sd = o.bias * o.nbar * r * (lam - static_cast<T>(nc)) / var;
-        }
-        cnt += 1.0;
-      }
+  // kU cells per thread and round (grid stride apart), all their inputs
+  // loaded before any is used and without a branch on the cell (indices
+  // clamped, the halo value and the count selected rather than guarded), so
+  // the loads of a round go out together.
+  constexpr int kU = 4;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; i0 < n; i0 += kU * st) {
+    T rv[kU], zv[kU], rr[kU], sv[kU];
+    int nv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * st < n ? i0 + u * st : n - 1;
+      // the data paint's z halo (layout [z / 8][x][y], grid side 2^lg)
+      // completes the cells z = 0 mod 8
+      zv[u] = zh ? zh[((i & ((1ll << lg) - 1)) >> 3 << (2 * lg)) | (i >> lg)] : T(0);
+      rr[u] = R ? R[i] : T(0);
+      nv[u] = counts ? counts[i] : 0;
+      sv[u] = s ? s[i] : T(0);
+      rv[u] = rho[i];
     }
-    if (seed) seed[i] = sd;
-    if (s) {
-      const double v = static_cast<double>(s[i]);
-      ss += v * v;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * st;
+      if (i >= n) continue;
+      const T rh = rv[u] + ((i & 7) == 0 ? zv[u] : T(0));
+      const T delta = rh - T(1);
+      const T r = rr[u];
+      T sd = T(0);
+      if (delta_out) delta_out[i] = delta;
+      if (R) {
+        T lam, dlam = T(0);
+        if (o.poisson) {
+          // u = 1 + delta is the painted density itself: taken from rho, not
+          // from 1 + (rho - 1), whose cancellation would leave nearly empty
+          // cells (u near the floor) with FP32 rounding of order 1e-7 / u
+          const T uu = rh > T(kUFloor) ? rh : T(kUFloor);
+          const T sig = T(1) / (T(1) + exp(-o.k * (delta - o.delta_th)));
+          const T ua = pow(uu, o.alpha);
+          lam = o.nbar * r * ua * sig;
+          const T du = rh > T(kUFloor) ? o.alpha * ua / uu : T(0);
+          dlam = o.nbar * r * (du * sig + ua * o.k * sig * (T(1) - sig));
+        } else {
+          lam = o.nbar * r * (T(1) + o.bias * delta);
+        }
+        if (lambda_out) lambda_out[i] = lam;
+        if (counts && r >= o.r_min) {
+          const int nc = nv[u];
+          if (o.poisson) {
+            const double l = static_cast<double>(lam), nn = static_cast<double>(nc);
+            chi += 2.0 * (l - nn * log(l) + lgamma(nn + 1.0));
+            sd = (T(1) - static_cast<T>(nc) / lam) * dlam;
+          } else {
+            const T var = o.nbar * r;
+            const double res = static_cast<double>(nc) - static_cast<double>(lam);
+            chi += res * res / static_cast<double>(var);
+            sd = o.bias * o.nbar * r * (lam - static_cast<T>(nc)) / var;
+          }
+          cnt += 1.0;
+        }
+      }
+      if (seed) seed[i] = sd;
+      if (s) {
+        const double v = static_cast<double>(sv[u]);
+        ss += v * v;
+      }
     }
   }
   chi = block_sum(chi, sh);
@@ -170,6 +189,7 @@ static __global__ __launch_bounds__(kRedThreads) void k_reduce_parts(const doubl
   __shared__ double sh[kRedThreads / 64];
   for (int k = 0; k < stride; ++k) {
     double v = 0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += part[stride * b + k];
     v = block_sum(v, sh);
     if (threadIdx.x == 0) out[k] = v;
