@@ -204,6 +204,7 @@ __global__ __launch_bounds__(kRedThreads) void k_absmax_parts(const T* __restric
                                                               double* __restrict__ part) {
   __shared__ double sh[kRedThreads / 64];
   double m = 0.0;
+#pragma unroll 4  // several iterations' loads in flight; same summation order
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     m = fmax(m, fabs(static_cast<double>(x[i])));
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dot(const T* __restrict__ a,
                                                      double* __restrict__ part, long long n) {
   __shared__ double sh[kRedThreads / 64];
   double acc = 0;
+#pragma unroll 4  // several iterations' loads in flight; same summation order
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const double x = static_cast<double>(a[i]);
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(kRedThreads) void k_dot_diff(const T* __restrict__ 
                                                           long long n) {
   __shared__ double sh[kRedThreads / 64];
   double acc = 0;
+#pragma unroll 4  // several iterations' loads in flight; same summation order
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     acc += static_cast<double>(g[i]) * (static_cast<double>(a[i]) - static_cast<double>(b[i]));
@@ -273,6 +276,7 @@ __global__ __launch_bounds__(kRedThreads) void k_centered_sq(const T* __restrict
   __shared__ double sh[kRedThreads / 64];
   const double mean = sum[0] / static_cast<double>(n);
   double acc = 0;
+#pragma unroll 4  // several iterations' loads in flight; same summation order
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const double x = static_cast<double>(a[i]) - mean;
@@ -301,11 +305,28 @@ __global__ __launch_bounds__(kRedThreads) void k_lbfgs_update(
   __shared__ double sh[kRedThreads / 64];
   const T c = static_cast<T>(cs * (d[ia] - (ib >= 0 ? fb * d[ib] : 0.0)));
   double acc = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    const T v = s_in * x[i] + c * X[i];
-    y[i] = v;
-    if (V) acc += static_cast<double>(V[i]) * static_cast<double>(v);
+  // kU elements per thread and round, loaded before any store (x may alias
+  // y, so the compiler would not move later loads above a store itself);
+  // the same elements in the same order as a plain grid-stride loop
+  constexpr int kU = 4;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; i0 < n; i0 += kU * st) {
+    T xv[kU], Xv[kU], Vv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * st < n ? i0 + u * st : n - 1;
+      xv[u] = x[i];
+      Xv[u] = X[i];
+      Vv[u] = V ? V[i] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * st;
+      if (i >= n) continue;
+      const T v = s_in * xv[u] + c * Xv[u];
+      y[i] = v;
+      if (V) acc += static_cast<double>(Vv[u]) * static_cast<double>(v);
+    }
   }
   if (!V) return;
   acc = block_sum(acc, sh);
@@ -443,6 +464,7 @@ __global__ __launch_bounds__(kRedThreads) void k_count_nonfinite(const T* __rest
                                                                  long long n) {
   __shared__ double sh[kRedThreads / 64];
   double bad = 0;
+#pragma unroll 4  // several iterations' loads in flight; same summation order
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     if (!isfinite(x[i])) bad += 1.0;
