@@ -444,14 +444,25 @@ __global__ __launch_bounds__(kRedThreads) void k_project(
   const double mean = sum[0] / static_cast<double>(n);
   const double sd = sqrt(sq[0] / static_cast<double>(n));
   double resets = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    T z = static_cast<T>((static_cast<double>(x[i]) - mean) / sd);
-    if (fabs(z) > s_th) {
-      z = static_cast<T>(philox_draw(0, (uint64_t)i, sub, 1, event, seed));
-      resets += 1.0;
+  // four elements per thread and round, loaded before any store (x may be
+  // out); the same elements in the same order as a plain grid-stride loop
+  constexpr int kU = 4;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; i0 < n; i0 += kU * st) {
+    T xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) xv[u] = x[i0 + u * st < n ? i0 + u * st : n - 1];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long i = i0 + u * st;
+      if (i >= n) continue;
+      T z = static_cast<T>((static_cast<double>(xv[u]) - mean) / sd);
+      if (fabs(z) > s_th) {
+        z = static_cast<T>(philox_draw(0, (uint64_t)i, sub, 1, event, seed));
+        resets += 1.0;
+      }
+      out[i] = z;
     }
-    out[i] = z;
   }
   resets = block_sum(resets, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = resets;
