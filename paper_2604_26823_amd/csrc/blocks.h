@@ -1117,6 +1117,47 @@ __global__ __launch_bounds__(kThreads) void k_force_adjoint_b(
   }
 }
 
+// Kick-synchronised snapshot of a state in its own block order (lightcone,
+// section 2.2.1 item 3): snap = (d, p + half_kick F(d)), six fields P apart,
+// F read out of the three force meshes g through the item's window.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_snapshot_b(
+    const T* __restrict__ d, const T* __restrict__ p, const T* __restrict__ g, long long M,
+    T half_kick, long long P, int lp, Grid<T> gm, Layout L, Items it, T* __restrict__ snap) {
+  __shared__ T lds[3 * kWin];
+  Item m;
+  if (!item_of<true>(it, L, m)) return;
+  long long a[kPer];
+  bool ok[kPer];
+  unsigned id[kPer];
+  int idx[kPer][3];
+  T dsp[kPer][3], mom[kPer][3];
+  item_slots(m, a, ok);  // particle loads in flight while the window loads
+  load_u32(it.ids, a, id);
+  load3_at(d, P, a, dsp);
+  load3_at(p, P, a, mom);
+  load_window<T>(m.o, L, Ptrs<T>{{g, g + M, g + 2 * M}}, 3, lds);
+  lattice_all(id, lp, idx);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    if (!ok[k]) continue;
+    T F[3] = {0, 0, 0};
+    const Stencil<T> s = wrapped_stencil(idx[k], dsp[k], gm);
+    pk::for_corners_xyz(s, [&](int cx, int cy, int cz, T w, T, T, T) {
+      const int c = win_index(m.o, cx, cy, cz);
+      F[0] += w * lds[c];
+      F[1] += w * lds[kWin + c];
+      F[2] += w * lds[2 * kWin + c];
+    });
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      snap[q * P + a[k]] = dsp[k][q];
+      snap[(3 + q) * P + a[k]] = mom[k][q] + half_kick * F[q];
+    }
+  }
+}
+
 // Last kick (readout of g at d) of the momenta p into pout in this order,
 // then the key and rank of the redshift-space position on the data grid
 // (layout Ld).  The momentum of slot a is p[a] (pout may then be p: each

@@ -952,9 +952,9 @@ class Engine final : public EngineBase {
       if (j >= 0) {
         // state n + 1 synchronised: p_{n+1/2} + K2_n F(d_{n+1})
         auto sc = timer_.scope("lc_snapshot", P_ * (12.0 * sizeT() + 4.0) + 3.0 * M_ * sizeT());
-        lk::k_snapshot<T><<<grid_for(P_, kThreads), kThreads, 0, st_>>>(
-            dslot(n + 1), pslot(n + 1), gslot(n + 1), M_, static_cast<T>(co_.K2[n]), ids(n + 1),
-            snap_ + (size_t)j * 6 * P_, P_, lp_, gmesh());
+        bk::k_snapshot_b<T><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
+            dslot(n + 1), pslot(n + 1), gslot(n + 1), M_, static_cast<T>(co_.K2[n]), P_, lp_,
+            gmesh(), Lm_, items(mesh_order(n + 1), ids(n + 1)), snap_ + (size_t)j * 6 * P_);
         IC_LAUNCHED();
       }
     }

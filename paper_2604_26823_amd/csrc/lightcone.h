@@ -195,31 +195,6 @@ __device__ __forceinline__ double crossing(const LcGeo& g, const pk::Rsd<T>& rsd
   return last;
 }
 
-// Kick-synchronised snapshot of state n, in its own block order (ids =
-// lattice id per slot): d, and p + half_kick F(d).
-template <typename T>
-__global__ __launch_bounds__(256) void k_snapshot(const T* __restrict__ d, const T* __restrict__ p,
-                                                  const T* __restrict__ g, long long M,
-                                                  T half_kick, const unsigned* __restrict__ ids,
-                                                  T* __restrict__ snap, long long P, int lp,
-                                                  pk::Grid<T> gm) {
-  for (long long a = blockIdx.x * (long long)blockDim.x + threadIdx.x; a < P;
-       a += (long long)gridDim.x * blockDim.x) {
-    int idx[3];
-    pk::lattice(static_cast<long long>(ids[a]), lp, idx);
-    T dsp[3], mom[3], F[3];
-    pk::load3(d, P, a, dsp);
-    pk::load3(p, P, a, mom);
-    const pk::Stencil<T> s = pk::stencil(idx, gm.ratio, dsp, gm.inv_cell, gm.cell);
-    pk::readout3(s, gm.lm, g, M, F);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      snap[q * P + a] = dsp[q];
-      snap[(3 + q) * P + a] = mom[q] + half_kick * F[q];
-    }
-  }
-}
-
 // inv[dest_{m+k-1}( ... dest_m(a))] = a for the count orders that follow the
 // snapshot's order m (dest: the first of count destination arrays, P apart):
 // the snapshot slot of every final slot.
