@@ -141,12 +141,6 @@ static __global__ __launch_bounds__(kThreads) void k_scatter(
   }
 }
 
-static __global__ void k_iota(uint32_t* __restrict__ v, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    v[i] = static_cast<uint32_t>(i);
-}
-
 template <typename T>
 __global__ void k_desc_keys(const T* __restrict__ x, uint64_t* __restrict__ keys,
                             uint32_t* __restrict__ vals, long long n) {
