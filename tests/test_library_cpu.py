@@ -136,3 +136,18 @@ def test_host_coefficients_match_oracle(lib, om, steps):
 def test_product_path_fails_loudly_without_library(tmp_path):
     with pytest.raises(_lib.NativeLibraryMissing):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_deterministic_mode_field(lib):
+    """ic_problem.deterministic: 0 by default, 0 or 1 accepted, and the mode
+    adds its integer paint fields (three mesh fields of 8 bytes per cell) and
+    eight doubles, in a 256-byte-aligned block of its own, to the workspace."""
+    p = api.make_problem(inputs.config(1))
+    assert p.deterministic == 0
+    base = _size(lib, inputs.config(1))[1]
+    rc, det = _size(lib, inputs.config(1, deterministic=1))
+    assert rc == 0 and det - base == 3 * 8 * 32 ** 3 + 256
+    p.deterministic = 2
+    size = ctypes.c_size_t()
+    assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
+    assert b"deterministic" in lib.ic_last_error(None)
