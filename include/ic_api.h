@@ -153,8 +153,8 @@ typedef struct ic_problem {
                             each cell's contributions as 64-bit integers with one
                             power-of-two scale per paint, chosen from the largest
                             contribution so that no sum of n_part^3 of them can
-                            overflow, and add them with integer atomics, whose order
-                            cannot change the sum; rounding each contribution to that
+                            overflow; integer sums do not depend on the order in which
+                            they are formed; rounding each contribution to that
                             scale (an absolute error of at most 2^-62 n_part^3 times the
                             largest contribution: 2^-38 of it at n_part = 256) is the
                             mode's only numerical change.

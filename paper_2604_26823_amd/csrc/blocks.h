@@ -717,45 +717,87 @@ __global__ __launch_bounds__(kThreads) void k_zero_unowned(const unsigned* __res
   }
 }
 
-// Output of a paint in deterministic mode: the integer field det (nf fields
-// of ncells, zeroed before the paint), the device maximum |v| the scale is
-// chosen for (null for a density paint) and lpc = log2 of the particle count.
+// Output of a paint in deterministic mode: the integer fields det (nf fields
+// of ncells), their z halo zh (nf x ncells / 8, laid out as a paint's z
+// halo) and x/y halo staging halo (nf x kHaloXY per item), the device
+// maximum |v| the scale is chosen for (null for a density paint) and lpc =
+// log2 of the particle count.
 struct DetOut {
   unsigned long long* det;
+  unsigned long long* zh;
+  unsigned long long* halo;
   const double* vmax;
   long long ncells;
   int lpc;
 };
 
-// Flush of a deterministic paint: every window cell's integer sum added
-// with a 64-bit integer atomic into det (nf fields of ncells, zeroed before
-// the paint).  Integer adds commute, so the result does not depend on the
-// order of the atomics nor on which particles share an item.
+// Flush of a deterministic paint: flush_owned's scheme with the windows'
+// integer sums themselves (one scale for the whole paint): a single item
+// stores its block's own cells and z-halo entries, the items of blocks with
+// several add theirs with 64-bit integer atomics (det and zh zeroed there
+// before the paint), and every item leaves its x/y halo in its staging
+// slot for k_halo_rows.  Integer adds commute, so the result depends neither
+// on the order of the atomics nor on which particles share an item.
 __device__ __forceinline__ void flush_det(const Item& m, const Layout& L, const FixAcc::Cell* acc,
-                                          int nf, unsigned long long* __restrict__ det,
-                                          long long ncells) {
-  for (int k = threadIdx.x; k < kWin; k += kThreads) {
-    const long long c = win_cell(m.o, k, L);
-    for (int f = 0; f < nf; ++f) {
-      const unsigned long long v = acc[f * kWin + k];
-      if (v) atomicAdd(det + f * ncells + c, v);
+                                          int nf, const DetOut& dt) {
+  constexpr int kIt = (kWin + kThreads - 1) / kThreads;
+  unsigned long long* hs = dt.halo + static_cast<size_t>(m.i) * nf * kHaloXY;
+  const long long zplane = 1ll << (2 * L.lm + L.lnb);  // zh values per field (n^3 / 8)
+  const unsigned bmask = (1u << L.lnb) - 1;
+#pragma unroll
+  for (int j = 0; j < kIt; ++j) {
+    const int k = static_cast<int>(threadIdx.x) + j * kThreads;
+    if (k >= kWin) continue;
+    const int kx = k / (kW * kW), r = k - kx * kW * kW;
+    const int ky = r / kW, kz = r - ky * kW;
+    if (kx < kB && ky < kB) {
+      unsigned long long* out;
+      long long c, fstride;
+      if (kz < kB) {
+        c = win_cell(m.o, k, L);
+        out = dt.det;
+        fstride = dt.ncells;
+      } else {
+        const unsigned bz = ((static_cast<unsigned>(m.o[2]) >> kLB) + 1) & bmask;
+        c = ((static_cast<long long>(bz) << L.lm | (m.o[0] + kx)) << L.lm) | (m.o[1] + ky);
+        out = dt.zh;
+        fstride = zplane;
+      }
+      for (int f = 0; f < nf; ++f) {
+        const unsigned long long v = acc[f * kWin + k];
+        if (m.single)
+          out[f * fstride + c] = v;
+        else if (v)
+          atomicAdd(out + f * fstride + c, v);
+      }
+    } else {
+      const int h = halo_xy_index(kx, ky, kz);
+      for (int f = 0; f < nf; ++f) hs[f * kHaloXY + h] = acc[f * kWin + k];
     }
   }
 }
 
-// The fields of a deterministic paint: out_f[i] = det[f ncells + i] 2^-e with
-// the paint's scale (vmax, coef, lpc as given to the paint).
+// The fields of a deterministic paint: out_f[i] = (det_f[i] + the z-halo
+// entry of cell i when its z is a multiple of 8) 2^-e with the paint's scale
+// (vmax, coef, lpc as given to the paint); lm = log2 of the grid side.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_det_to_field(const unsigned long long* __restrict__ det,
-                                                           int nf, long long ncells,
+                                                           const unsigned long long* __restrict__ zh,
+                                                           int nf, long long ncells, int lm,
                                                            const double* __restrict__ vmax,
                                                            T coef, int lpc, MPtrs<T> out) {
   const double inv = FixAcc::scale_det(det_amax<T>(vmax, coef), lpc).inv;
+  const long long zplane = ncells >> kLB;
   for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < ncells;
-       i += (long long)gridDim.x * kThreads)
-    for (int f = 0; f < nf; ++f)
-      out.p[f][i] =
-          static_cast<T>(static_cast<double>(static_cast<long long>(det[f * ncells + i])) * inv);
+       i += (long long)gridDim.x * kThreads) {
+    const long long zi = ((i & ((1ll << lm) - 1)) >> kLB << (2 * lm)) | (i >> lm);
+    const bool zcell = (i & (kB - 1)) == 0;
+    for (int f = 0; f < nf; ++f) {
+      const unsigned long long z = zh[f * zplane + zi];
+      const unsigned long long v = det[f * ncells + i] + (zcell ? z : 0ull);
+      out.p[f][i] = static_cast<T>(static_cast<double>(static_cast<long long>(v)) * inv);
+    }
+  }
 }
 
 // Cells that receive x/y halo values: those with x or y on a block's lowest
@@ -912,7 +954,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_b(const T* __restrict__ d,
   }
   __syncthreads();
   if constexpr (DET)
-    flush_det(m, L, acc, 1, dt.det, dt.ncells);
+    flush_det(m, L, acc, 1, dt);
   else
     flush_owned<T>(m, L, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }
@@ -980,7 +1022,7 @@ __global__ __launch_bounds__(kThreads) void k_paint_vec_b(const T* __restrict__ 
   }
   __syncthreads();
   if constexpr (DET)
-    flush_det(m, L, acc, 3, dt.det, dt.ncells);
+    flush_det(m, L, acc, 3, dt);
   else
     flush_owned<T>(m, L, acc, sc, 3, MPtrs<T>{{out, out + M, out + 2 * M}}, zh, halo);
 }
@@ -1284,7 +1326,7 @@ __global__ __launch_bounds__(kThreads) void k_data_paint_b(const T* __restrict__
   }
   __syncthreads();
   if constexpr (DET)
-    flush_det(m, Ld, acc, 1, dt.det, dt.ncells);
+    flush_det(m, Ld, acc, 1, dt);
   else
     flush_owned<T>(m, Ld, acc, sc, 1, MPtrs<T>{{rho}}, zh, halo);
 }

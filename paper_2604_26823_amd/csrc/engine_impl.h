@@ -147,15 +147,19 @@ class Engine final : public EngineBase {
     // painted field (three mesh fields; the data grid's apart, since the
     // loss reads it after the adjoint's paints began)
     hstage_ = c.take<T>((size_t)std::max<long long>(3ll * mim_, mid_) * bk::kHaloXY);
-    zh_ = c.take<T>(3 * M_ / kZHalo);
-    zhd_ = c.take<T>(P_ / kZHalo);
-    // deterministic mode: the paints' integer accumulation fields (three mesh
-    // fields, or the data grid) and the device maximum their scale is for
     det_ = p.deterministic != 0;
     if (det_) {
+      // deterministic mode: the paints' integer fields (three mesh fields, or
+      // the data grid), their z halo and x/y halo staging, and the device
+      // maximum the cotangent paint's scale is chosen for
       det64_ = c.take<unsigned long long>(3 * std::max(M_, P_));
+      detzh_ = c.take<unsigned long long>(3 * std::max(M_, P_) / kZHalo);
+      detstage_ =
+          c.take<unsigned long long>((size_t)std::max<long long>(3ll * mim_, mid_) * bk::kHaloXY);
       detvmax_ = c.take<double>(8);
     }
+    zh_ = c.take<T>(3 * M_ / kZHalo);
+    zhd_ = c.take<T>(P_ / kZHalo);
     tmpd_ = c.take<T>(3 * P_);
     tmpp_ = c.take<T>(3 * P_);
     dsd_ = c.take<T>(3 * P_);
@@ -183,6 +187,8 @@ class Engine final : public EngineBase {
     if (ws_bytes < need_) throw ApiError(IC_ERR_WORKSPACE, "workspace too small");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
       throw ApiError(IC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (det_ && !(det64_ && detzh_ && detstage_ && detvmax_))
+      throw ApiError(IC_ERR_STATE, "deterministic-mode buffers missing from the workspace");
     timer_.set_stream(st_);
     for (int i = 0; i <= m; ++i) free_slots_.push_back(i);
 
@@ -678,15 +684,33 @@ class Engine final : public EngineBase {
   // work item; the fields are then converted and left complete (their z
   // halo buffers zeroed, no x/y halo pass).
   bk::DetOut det_out(const double* vmax, long long ncells) const {
-    return bk::DetOut{det64_, vmax, ncells, 3 * lp_};
+    return bk::DetOut{det64_, detzh_, detstage_, vmax, ncells, 3 * lp_};
   }
-  void fill_det(long long n) {
-    fk::k_fill<unsigned long long><<<grid_for(n, kThreads), kThreads, 0, st_>>>(det64_, 0ull, n);
+  bk::MPtrs<unsigned long long> det_fields(long long ncells) const {
+    return bk::MPtrs<unsigned long long>{{det64_, det64_ + ncells, det64_ + 2 * ncells}};
+  }
+  // Before a deterministic paint of order o: the integer cells and z-halo
+  // entries that no single work item stores.
+  void det_zero_unowned(const Order& o, const bk::Layout& L, int nf, long long ncells) {
+    const long long nb = 1ll << (3 * L.lnb);
+    bk::k_zero_unowned<unsigned long long>
+        <<<grid_for(nb * 64, bk::kThreads, 1u << 30), bk::kThreads, 0, st_>>>(
+            o.istart, L, nf, det_fields(ncells), detzh_);
     IC_LAUNCHED();
   }
-  void det_to_field(const double* vmax, T coef, int nf, long long ncells, const bk::MPtrs<T>& out) {
+  // After it: the x/y halo staging into the integer cells, then the fields.
+  void det_finish(const Order& o, const bk::Layout& L, const double* vmax, T coef, int nf,
+                  long long ncells, const bk::MPtrs<T>& out) {
+    const unsigned grid = grid_for(bk::face_waves(L) * 64, bk::kThreads, 1u << 30);
+    if (nf == 3)
+      bk::k_halo_rows<unsigned long long, 3>
+          <<<grid, bk::kThreads, 0, st_>>>(detstage_, o.istart, L, det_fields(ncells));
+    else
+      bk::k_halo_rows<unsigned long long, 1>
+          <<<grid, bk::kThreads, 0, st_>>>(detstage_, o.istart, L, det_fields(ncells));
+    IC_LAUNCHED();
     bk::k_det_to_field<T><<<grid_for(ncells, bk::kThreads), bk::kThreads, 0, st_>>>(
-        det64_, nf, ncells, vmax, coef, 3 * lp_, out);
+        det64_, detzh_, nf, ncells, L.lm, vmax, coef, 3 * lp_, out);
     IC_LAUNCHED();
   }
   // *out = max |x_i| over n values.
@@ -708,7 +732,7 @@ class Engine final : public EngineBase {
     const double bytes = P_ * ((gsrc ? 6.0 : 3.0) * sizeT() + (gsrc ? 8.0 : 4.0)) +
                          2.0 * ncells * sizeT();
     if (det_) {
-      fill_det(ncells);
+      det_zero_unowned(o, L, 1, ncells);
       {
         auto sc = timer_.scope("cic_paint", bytes);
         bk::k_paint_b<T, true><<<o.max_items + 8, bk::kThreads, 0, st_>>>(
@@ -716,8 +740,8 @@ class Engine final : public EngineBase {
             det_out(nullptr, ncells));
         IC_LAUNCHED();
       }
-      det_to_field(nullptr, T(1), 1, ncells, bk::MPtrs<T>{{rho}});
-      fill(zh, T(0), ncells / kZHalo);
+      det_finish(o, L, nullptr, T(1), 1, ncells, bk::MPtrs<T>{{rho}});
+      fill(zh, T(0), ncells / kZHalo);  // the halo is in rho already
       return;
     }
     zero_unowned(o, L, 1, bk::MPtrs<T>{{rho}}, zh);
@@ -1004,7 +1028,7 @@ class Engine final : public EngineBase {
     scatter(data_order(), state_ptrs(fd, fp), state_mptrs(dsd_, psd_), 6, ids(S_), dids_,
             dest(S_));
     if (det_) {
-      fill_det(P_);
+      det_zero_unowned(data_order(), Ld_, 1, P_);
       {
         auto sc = timer_.scope("data_paint", P_ * (8.0 * sizeT() + 4.0) + 2.0 * P_ * sizeT());
         bk::k_data_paint_b<T, true><<<bk::item_grid(Ld_, P_), bk::kThreads, 0, st_>>>(
@@ -1012,8 +1036,8 @@ class Engine final : public EngineBase {
             hstage_, det_out(nullptr, P_));
         IC_LAUNCHED();
       }
-      det_to_field(nullptr, T(1), 1, P_, bk::MPtrs<T>{{rhod_}});
-      fill(zhd_, T(0), P_ / kZHalo);
+      det_finish(data_order(), Ld_, nullptr, T(1), 1, P_, bk::MPtrs<T>{{rhod_}});
+      fill(zhd_, T(0), P_ / kZHalo);  // the halo is in rhod_ already
       return;
     }
     zero_unowned(data_order(), Ld_, 1, bk::MPtrs<T>{{rhod_}}, zhd_);
@@ -1168,7 +1192,7 @@ class Engine final : public EngineBase {
       const bk::MPtrs<T> gb{{gbar_, gbar_ + M_, gbar_ + 2 * M_}};
       if (det_) {
         absmax(pbar_, 3 * P_, detvmax_);  // the paint's scale: max |p_bar| over all slots
-        fill_det(3 * M_);
+        det_zero_unowned(mesh_order(n), Lm_, 3, M_);
         {
           auto sc = timer_.scope("cic_paint_vec", P_ * (6.0 * sizeT() + 8.0) + 6.0 * M_ * sizeT());
           bk::k_paint_vec_b<T, true><<<bk::item_grid(Lm_, P_), bk::kThreads, 0, st_>>>(
@@ -1176,8 +1200,8 @@ class Engine final : public EngineBase {
               det_out(detvmax_, M_));
           IC_LAUNCHED();
         }
-        det_to_field(detvmax_, coef, 3, M_, gb);
-        fill(zh_, T(0), 3 * M_ / kZHalo);
+        det_finish(mesh_order(n), Lm_, detvmax_, coef, 3, M_, gb);
+        fill(zh_, T(0), 3 * M_ / kZHalo);  // the halo is in the meshes already
       } else {
         zero_unowned(mesh_order(n), Lm_, 3, gb, zh_);
         {
@@ -1338,6 +1362,8 @@ class Engine final : public EngineBase {
   T* zhd_ = nullptr;
   bool det_ = false;                       // deterministic mode
   unsigned long long* det64_ = nullptr;    // its integer paint fields
+  unsigned long long* detzh_ = nullptr;    // their z halo
+  unsigned long long* detstage_ = nullptr; // their x/y halo staging
   double* detvmax_ = nullptr;              // its cotangent paint's max |p_bar|
   static_assert(bk::kB == kZHalo, "the z halo spacing is the block side");
   T *tmpd_, *tmpp_, *dsd_, *psd_, *dbar2_, *pbar2_;

@@ -140,13 +140,19 @@ def test_product_path_fails_loudly_without_library(tmp_path):
 
 def test_deterministic_mode_field(lib):
     """ic_problem.deterministic: 0 by default, 0 or 1 accepted, and the mode
-    adds its integer paint fields (three mesh fields of 8 bytes per cell) and
-    eight doubles, in a 256-byte-aligned block of its own, to the workspace."""
+    adds to the workspace its integer paint fields (three mesh fields of 8
+    bytes per cell), their z halo (one value per 8 cells), their x/y halo
+    staging (153 cells of three fields per work item of the mesh orders,
+    items = ceil(n^3 / 1024) + (n / 8)^3) and eight doubles (a 256-byte
+    block)."""
     p = api.make_problem(inputs.config(1))
     assert p.deterministic == 0
+    n = 32
+    items = -(-n ** 3 // 1024) + (n // 8) ** 3
     base = _size(lib, inputs.config(1))[1]
     rc, det = _size(lib, inputs.config(1, deterministic=1))
-    assert rc == 0 and det - base == 3 * 8 * 32 ** 3 + 256
+    assert rc == 0
+    assert det - base == 3 * 8 * n ** 3 + 3 * n ** 3 + 3 * items * 153 * 8 + 256
     p.deterministic = 2
     size = ctypes.c_size_t()
     assert lib.ic_workspace_size(ctypes.byref(p), _lib.IC_F32, ctypes.byref(size)) == -1
